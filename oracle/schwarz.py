@@ -1,0 +1,184 @@
+"""Extended-element subdomains and the weighted additive Schwarz smoother
+(Section 3.1, Algorithm 2).
+
+Subdomain of element e (per direction): the element's p+1 nodes plus n_o node
+layers taken from each neighbour; the next node outward lies on the subdomain
+boundary and is excluded, so in global node numbering the subdomain is
+[e p - n_o, (e+1) p + n_o] (m = p + 1 + 2 n_o nodes).  With Dirichlet
+boundaries, nodes on or beyond the domain boundary are not unknowns and are
+dropped; with periodic boundaries indices wrap.
+
+Local problem (eq. subproblem): A_ss du_s = r_s with A_ss = R_s A R_s^T, the
+principal submatrix of A on the subdomain's unknowns.  Because the subdomain
+is a Cartesian product of 1-D index sets, A_ss = M_sy (x) L_sx + L_sy (x) M_sx
+with L_s*, M_s* the principal submatrices of the 1-D matrices.  The oracle
+solves it with a dense factorisation (the definition); ``fdm_solve`` is the
+paper's fast-diagonalisation formula, kept for the tests that pin the two
+against each other.
+
+Variable diffusion (Section 4): du_s ~ (1/nu_bar_s) A_ss^{-1} r_s with nu_bar_s
+the mean of nu over the embedded element (eq. subproblem solution).
+
+Combination (eq. correction global, Algorithm 2): u <- u + sum_s R_s^T W_s du_s
+with W_s = W_y (x) W_x from the weight function, or W_s = R_s C^+ R_s^T with C
+the counting matrix for arithmetic averaging.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .discretization import DIRICHLET, PERIODIC, Axis, Space
+from .weights import WF_ARITH, overlap_width, weight
+
+
+class Subdomain1D:
+    """Index set and extended coordinates of one subdomain in one direction."""
+
+    def __init__(self, axis: Axis, L: np.ndarray, M: np.ndarray, e: int, n_o: int,
+                 alpha_left: float = 1.0, alpha_right: float = 1.0):
+        p = axis.p
+        if not 0 <= n_o <= p - 1:
+            raise ValueError("n_o must lie in [0, p-1]")
+        xi = axis.xi
+        self.e = e
+        self.n_o = n_o
+        self.m = p + 1 + 2 * n_o
+        glob, xext, valid = [], [], []
+        for t in range(-n_o, p + n_o + 1):
+            if t < 0:
+                x = xi[p + t] - 2.0          # node of the left neighbour
+            elif t > p:
+                x = xi[t - p] + 2.0          # node of the right neighbour
+            else:
+                x = xi[t]
+            g = e * p + t
+            if axis.bc == PERIODIC:
+                g %= axis.N
+                ok = True
+            else:
+                ok = 1 <= g <= axis.N - 2
+            glob.append(g)
+            xext.append(x)
+            valid.append(ok)
+        self.valid = np.array(valid)
+        self.glob = np.array(glob)[self.valid]
+        self.xi_ext = np.array(xext)[self.valid]
+        self.Ls = L[np.ix_(self.glob, self.glob)]
+        self.Ms = M[np.ix_(self.glob, self.glob)]
+        delta = overlap_width(xi, n_o)
+        self.delta_left = alpha_left * delta
+        self.delta_right = alpha_right * delta
+        self.left_sat = axis.bc == DIRICHLET and e == 0
+        self.right_sat = axis.bc == DIRICHLET and e == axis.n - 1
+
+    def key(self):
+        return (self.Ls.shape[0], self.Ls.tobytes(), self.Ms.tobytes())
+
+    def weights(self, kappa: int) -> np.ndarray:
+        return weight(kappa, self.xi_ext, self.delta_left, self.delta_right,
+                      self.left_sat, self.right_sat)
+
+
+def local_matrix(sy: Subdomain1D, sx: Subdomain1D) -> np.ndarray:
+    """A_ss = M_sy (x) L_sx + L_sy (x) M_sx (row-major: y slow, x fast)."""
+    return np.kron(sy.Ms, sx.Ls) + np.kron(sy.Ls, sx.Ms)
+
+
+def fdm_factors(Ls: np.ndarray, Ms: np.ndarray):
+    """Generalised eigenproblem L_s S = M_s S Lambda with S^T M_s S = I
+    (M_s is diagonal and positive)."""
+    d = 1.0 / np.sqrt(np.diag(Ms))
+    lam, Q = np.linalg.eigh(d[:, None] * Ls * d[None, :])
+    return d[:, None] * Q, lam
+
+
+def fdm_solve(sy: Subdomain1D, sx: Subdomain1D, Rs: np.ndarray) -> np.ndarray:
+    """Fast diagonalisation (Section 3.1):
+    A_ss^{-1} = (S_y (x) S_x)(I (x) Lambda_x + Lambda_y (x) I)^{-1}(S_y^T (x) S_x^T)."""
+    Sx, lx = fdm_factors(sx.Ls, sx.Ms)
+    Sy, ly = fdm_factors(sy.Ls, sy.Ms)
+    T = Sy.T @ Rs @ Sx
+    T = T / (ly[:, None] + lx[None, :])
+    return Sy @ T @ Sx.T
+
+
+class SchwarzLevel:
+    """All subdomains of one level, grouped by identical local matrices."""
+
+    def __init__(self, space: Space, n_o: int, wf: int = 5,
+                 alpha_x=None, alpha_y=None):
+        """alpha_x[I], alpha_y[J]: optional width scales per grid line
+        (interface I between elements I-1 and I); 1 reproduces the paper."""
+        self.space = space
+        self.n_o = n_o
+        self.wf = wf
+        ax, ay = space.ax, space.ay
+        nlx = ax.n + 1
+        nly = ay.n + 1
+        alpha_x = np.ones(nlx) if alpha_x is None else np.asarray(alpha_x, dtype=np.float64)
+        alpha_y = np.ones(nly) if alpha_y is None else np.asarray(alpha_y, dtype=np.float64)
+        if ax.bc == PERIODIC:
+            alpha_x = alpha_x.copy()
+            alpha_x[-1] = alpha_x[0]
+        if ay.bc == PERIODIC:
+            alpha_y = alpha_y.copy()
+            alpha_y[-1] = alpha_y[0]
+        self.sx = [Subdomain1D(ax, space.Lx, space.Mx, e, n_o, alpha_x[e], alpha_x[e + 1])
+                   for e in range(ax.n)]
+        self.sy = [Subdomain1D(ay, space.Ly, space.My, e, n_o, alpha_y[e], alpha_y[e + 1])
+                   for e in range(ay.n)]
+        if wf == WF_ARITH:
+            self.count = counting_matrix(self)
+        # group subdomains by their local matrices; one dense inverse per group
+        groups = {}
+        for ey in range(ay.n):
+            for ex in range(ax.n):
+                k = (self.sy[ey].key(), self.sx[ex].key())
+                groups.setdefault(k, []).append((ey, ex))
+        self.groups = []
+        for members in groups.values():
+            ey0, ex0 = members[0]
+            A_ss = local_matrix(self.sy[ey0], self.sx[ex0])
+            Ainv = np.linalg.inv(A_ss)
+            gy = np.array([self.sy[ey].glob for ey, _ in members])
+            gx = np.array([self.sx[ex].glob for _, ex in members])
+            W = np.array([self.subdomain_weights(ey, ex) for ey, ex in members])
+            self.groups.append((members, Ainv, gy, gx, W))
+
+    def subdomain_weights(self, ey: int, ex: int) -> np.ndarray:
+        sy, sx = self.sy[ey], self.sx[ex]
+        if self.wf == WF_ARITH:
+            return 1.0 / self.count[np.ix_(sy.glob, sx.glob)]
+        return np.outer(sy.weights(self.wf), sx.weights(self.wf))
+
+    def corrections(self, R: np.ndarray, nubar=None) -> np.ndarray:
+        """sum_s R_s^T W_s A_ss^{-1} R_s r (divided by nu_bar_s if given)."""
+        dU = np.zeros(self.space.shape)
+        for members, Ainv, gy, gx, W in self.groups:
+            Rs = R[gy[:, :, None], gx[:, None, :]]
+            n, my, mx = Rs.shape
+            D = (Rs.reshape(n, my * mx) @ Ainv.T).reshape(n, my, mx)
+            if nubar is not None:
+                D = D / np.array([nubar[ey, ex] for ey, ex in members])[:, None, None]
+            np.add.at(dU, (gy[:, :, None], gx[:, None, :]), W * D)
+        return dU
+
+    def smooth(self, U, F, n_it: int, NU=None, nubar=None):
+        """Algorithm 2 (WSchwarz): n_it sweeps of r = f - A u, u += sum_s ...
+        With NU given, the residual uses B(nu) and the local solves nu_bar."""
+        sp = self.space
+        for _ in range(n_it):
+            R = F - (sp.apply_A(U) if NU is None else sp.apply_B(U, NU))
+            R = sp.zero_boundary(R)
+            U = U + self.corrections(R, nubar)
+        return U
+
+
+def counting_matrix(level: SchwarzLevel) -> np.ndarray:
+    """C = sum_s R_s^T R_s: how many subdomains contain each unknown."""
+    C = np.zeros(level.space.shape)
+    for sy in level.sy:
+        for sx in level.sx:
+            C[np.ix_(sy.glob, sx.glob)] += 1.0
+    C[~level.space.mask] = 1.0
+    return C

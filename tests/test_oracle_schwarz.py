@@ -1,0 +1,172 @@
+"""Pins of the oracle's Schwarz components: shape functions (Table 1), weight
+function (Section 3.1), subdomain matrices and local solves."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.discretization import DIRICHLET, PERIODIC, Space
+from oracle.gll import gll
+from oracle.schwarz import SchwarzLevel, fdm_solve, local_matrix
+from oracle.weights import TABLE1, WF_ARITH, WF_TOPHAT, overlap_width, phi, phi_hat_integral, weight
+from paper_1512_02390_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("kappa", [1, 3, 5, 7, 9])
+def test_shape_function_conditions(kappa):
+    """phi^(+-1) = +-1, derivatives of order 1..(kappa-1)/2 vanish at +-1,
+    strictly increasing on (-1, 1).  Derivatives come from an exact polynomial
+    fit of the function as implemented, so a wrong coefficient fails."""
+    f = TABLE1[kappa] if kappa in TABLE1 else (lambda x: phi_hat_integral(kappa, x))
+    assert abs(f(1.0) - 1.0) < 1e-14 and abs(f(-1.0) + 1.0) < 1e-14
+    coeffs = np.polynomial.polynomial.polyfit(np.linspace(-1, 1, 41), f(np.linspace(-1, 1, 41)), kappa)
+    poly = np.polynomial.Polynomial(coeffs)
+    for k in range(1, (kappa - 1) // 2 + 1):
+        d = poly.deriv(k)
+        assert abs(d(1.0)) < 1e-6 and abs(d(-1.0)) < 1e-6
+    t = np.linspace(-1, 1, 2001)
+    assert np.all(np.diff(f(t)) > 0)
+
+
+@pytest.mark.parametrize("kappa", [1, 3, 5, 7])
+def test_table1_equals_integral_form(kappa):
+    t = np.linspace(-1, 1, 101)
+    assert np.allclose(TABLE1[kappa](t), phi_hat_integral(kappa, t), atol=1e-14)
+
+
+def test_shape_function_outside_is_sign():
+    x = np.array([-3.0, -1.5, 1.2, 7.0])
+    for k in (1, 3, 5, 7, WF_TOPHAT):
+        assert np.array_equal(phi(k, x), np.sign(x))
+
+
+def test_overlap_width_closed_forms():
+    assert overlap_width(gll(4)[0], 1) == pytest.approx(1.0, abs=1e-15)
+    assert overlap_width(gll(8)[0], 3) == pytest.approx(1.0, abs=1e-15)
+    assert overlap_width(gll(2)[0], 1) == pytest.approx(2.0, abs=1e-15)
+    assert overlap_width(gll(3)[0], 0) == pytest.approx(1.0 - 1.0 / math.sqrt(5), abs=1e-15)
+
+
+def test_worked_example_weights():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "weights_p4_no1.txt"))
+            if l.strip() and not l.startswith("#")]
+    xb = W.uniform_breaks(5, 1.0)
+    lev = SchwarzLevel(Space(xb, xb, 4, PERIODIC), 1, 5)
+    s = lev.sx[2]
+    for r in rows:
+        kappa = int(r[0])
+        ref = np.array([float(v) for v in r[1:]])
+        got = weight(kappa, s.xi_ext, s.delta_left, s.delta_right)
+        assert np.allclose(got, ref, atol=1e-6), (kappa, got)
+
+
+def test_top_hat_pattern():
+    xb = W.uniform_breaks(4, 1.0)
+    lev = SchwarzLevel(Space(xb, xb, 6, PERIODIC), 2, WF_TOPHAT)
+    w = lev.sx[1].weights(WF_TOPHAT)
+    x = lev.sx[1].xi_ext
+    assert np.all(w[np.abs(x) < 1 - 1e-12] == 1.0)
+    assert np.all(w[np.abs(np.abs(x) - 1) < 1e-12] == 0.5)
+    assert np.all(w[np.abs(x) > 1 + 1e-12] == 0.0)
+
+
+CASES = [(p, n_o, bc, wf) for p in (2, 3, 4, 6, 8) for n_o in range(0, p)
+         for bc in (DIRICHLET, PERIODIC) for wf in (1, 3, 5, 7, WF_TOPHAT, WF_ARITH)]
+
+
+@pytest.mark.parametrize("p,n_o,bc,wf", CASES[::3])
+def test_partition_of_unity(p, n_o, bc, wf):
+    """sum_s R_s^T W_s R_s = I on the unknowns, on a stretched mesh."""
+    xb = W.geometric_breaks(4, 0.25, 3.0)
+    yb = W.uniform_breaks(3, 1.0)
+    lev = SchwarzLevel(Space(xb, yb, p, bc), n_o, wf)
+    S = np.zeros(lev.space.shape)
+    for ey, ex in itertools.product(range(3), range(4)):
+        sy, sx = lev.sy[ey], lev.sx[ex]
+        S[np.ix_(sy.glob, sx.glob)] += lev.subdomain_weights(ey, ex)
+    assert np.allclose(S[lev.space.mask], 1.0, atol=1e-14)
+
+
+def test_partition_of_unity_with_width_scales():
+    xb = W.uniform_breaks(5, 1.0)
+    rng = np.random.default_rng(0)
+    ax_ = rng.uniform(0.2, 1.0, 6)
+    ay_ = rng.uniform(0.2, 1.0, 6)
+    for bc in (DIRICHLET, PERIODIC):
+        lev = SchwarzLevel(Space(xb, xb, 8, bc), 2, 5, ax_, ay_)
+        S = np.zeros(lev.space.shape)
+        for ey, ex in itertools.product(range(5), range(5)):
+            S[np.ix_(lev.sy[ey].glob, lev.sx[ex].glob)] += lev.subdomain_weights(ey, ex)
+        assert np.allclose(S[lev.space.mask], 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("p,n_o", [(4, 1), (6, 1), (8, 1), (8, 2), (16, 2), (3, 0)])
+def test_arithmetic_weights_match_formula_on_open_interval(p, n_o):
+    """W = R_s C^+ R_s^T (counting) equals the weight function with phi^ = 0
+    whenever the node on |arg| = 1 is not an unknown of the subdomain."""
+    xb = W.uniform_breaks(4, 1.0)
+    lev = SchwarzLevel(Space(xb, xb, p, PERIODIC), n_o, WF_ARITH)
+    s = lev.sx[1]
+    d = s.delta_left
+    if d <= 1.0 and np.min(np.abs(np.abs(s.xi_ext) - 1 - d)) > 1e-9 \
+            and np.min(np.abs(np.abs(s.xi_ext) - (1 - d))) > 1e-9:
+        w_formula = weight(WF_ARITH, s.xi_ext, d, d)
+        w_count = lev.subdomain_weights(1, 1)
+        assert np.allclose(np.outer(w_formula, w_formula), w_count, atol=1e-15)
+
+
+def _tiny_cases():
+    for p in (2, 3, 4, 5):
+        for n_o in range(p):
+            for bc in (DIRICHLET, PERIODIC):
+                yield p, n_o, bc
+
+
+@pytest.mark.parametrize("p,n_o,bc", list(_tiny_cases()))
+def test_local_matrix_is_principal_submatrix_and_fdm_inverts_it(p, n_o, bc):
+    """A_ss built from the restricted 1-D matrices equals the principal submatrix
+    of the element-assembled global matrix; the fast-diagonalisation formula
+    gives the same solution as a dense solve with it."""
+    xb = W.geometric_breaks(3, 0.2, 2.5)
+    yb = W.uniform_breaks(3, 0.8)
+    sp = Space(xb, yb, p, bc)
+    lev = SchwarzLevel(sp, n_o, 5)
+    A = sp.dense_B(np.ones(sp.shape))
+    num = -np.ones(sp.shape, dtype=int)
+    num[sp.mask] = np.arange(sp.mask.sum())
+    rng = np.random.default_rng(p * 10 + n_o)
+    for ey, ex in [(0, 0), (1, 1), (2, 1), (1, 2)]:
+        sy, sx = lev.sy[ey], lev.sx[ex]
+        ids = num[np.ix_(sy.glob, sx.glob)].ravel()
+        assert np.all(ids >= 0)
+        Ass = local_matrix(sy, sx)
+        assert np.allclose(Ass, A[np.ix_(ids, ids)], atol=1e-12 * np.abs(A).max())
+        R = rng.standard_normal((len(sy.glob), len(sx.glob)))
+        d_dense = np.linalg.solve(Ass, R.ravel()).reshape(R.shape)
+        d_fdm = fdm_solve(sy, sx, R)
+        assert np.allclose(d_fdm, d_dense, rtol=0, atol=1e-12 * np.abs(d_dense).max())
+
+
+def test_single_element_smoother_is_exact_solve():
+    """One Dirichlet element: the subdomain is the whole domain and W = 1, so
+    one WSchwarz sweep solves the system."""
+    for p in (3, 6, 9):
+        sp = Space([0.0, 1.0], [0.0, 2.0], p, DIRICHLET)
+        lev = SchwarzLevel(sp, p - 1, 5)
+        F = W.random_nodal(sp.shape, DIRICHLET, 3)
+        U = lev.smooth(np.zeros(sp.shape), F, 1)
+        assert np.abs(F - sp.apply_A(U))[sp.mask].max() < 1e-12 * np.abs(F).max()
+
+
+def test_nu_bar_scaling_of_corrections():
+    xb = W.uniform_breaks(3, 1.0)
+    sp = Space(xb, xb, 4, PERIODIC)
+    lev = SchwarzLevel(sp, 1, 5)
+    R = W.random_nodal(sp.shape, PERIODIC, 8)
+    c1 = lev.corrections(R)
+    c2 = lev.corrections(R, 4.0 * np.ones((3, 3)))
+    assert np.allclose(c2, c1 / 4.0, atol=1e-15)
