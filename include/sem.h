@@ -1,0 +1,159 @@
+/*
+ * sem.h -- C-ABI of the MI355X hybrid Schwarz / p-multigrid solver for the
+ * spectral element discretisation of
+ *      -div(nu grad u) = f   on a Cartesian mesh of rectangular elements
+ * (Poisson when nu = 1), after J. Stiller, "Nonuniformly weighted Schwarz
+ * smoothers for spectral element multigrid" (arXiv 1512.02390).
+ *
+ * Conventions shared by every entry point
+ *  - Vectors are nodal arrays of one multigrid level, FP64, row-major with
+ *    rows along y and columns along x, `rows * cols` contiguous doubles in
+ *    device memory (sizes from sem_layout).  Dirichlet arrays include the
+ *    boundary nodes; their entries are ignored on input and written as 0.
+ *    Periodic arrays hold n*p nodes per direction (node n*p is node 0).
+ *  - The caller owns every vector passed in; the handle owns all tables and
+ *    internal level vectors.
+ *  - Work is queued on the HIP stream given to sem_setup and is asynchronous
+ *    unless stated otherwise.  A handle is not thread-safe; use one handle
+ *    per stream.
+ *  - Every function returns a sem_status; no C++ exception crosses the ABI.
+ *    sem_last_error() describes the most recent failure of a handle.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx *sem_handle;
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_EINVAL = -1,   /* invalid argument (sizes, null pointer, overlap range) */
+  SEM_EDOM = -2,     /* nu <= 0 or non-increasing element breaks           */
+  SEM_ENOMEM = -3,   /* device or host allocation failed                  */
+  SEM_EHIP = -4,     /* a HIP runtime call failed                          */
+  SEM_ENOCONV = -5,  /* pcg_solve reached imax; u holds the last iterate   */
+  SEM_ENAN = -6,     /* non-finite residual encountered                    */
+  SEM_EUNSUP = -7    /* supported by the method but not by this build
+                        (tile size, coarse grid too large for nu != 1)     */
+} sem_status;
+
+typedef enum { SEM_BC_DIRICHLET = 0, SEM_BC_PERIODIC = 1 } sem_bc;
+
+/* Weight functions of Table 1 (Section 3.1).  Odd kappa >= 1 selects the
+ * smoothed sign function of that order (1 linear, 3 cubic, 5 quintic,
+ * 7 seventh order, larger odd orders by the same defining conditions). */
+typedef enum { SEM_W_TOPHAT = -1, SEM_W_ARITH = -2 } sem_wf_special;
+
+/* Overlap n_o per multigrid level l > 0 (Section 4); always clamped to
+ * [0, p_l - 1]. */
+typedef enum {
+  SEM_NO_FIXED = 0,   /* n_o on every level              */
+  SEM_NO_CEIL_P8 = 1, /* ceil(p_l / 8)  (the paper's recommendation) */
+  SEM_NO_FLOOR_P8 = 2,/* floor(p_l / 8) */
+  SEM_NO_CEIL_P2 = 3  /* ceil(p_l / 2)  */
+} sem_overlap_rule;
+
+/* Arithmetic of the V-cycle used as preconditioner.  Vectors crossing the
+ * ABI are always FP64.  SEM_MIXED_FP32 runs smoother, transfers and coarse
+ * levels in FP32 inside an FP64 residual / CG outer iteration. */
+typedef enum { SEM_FP64 = 0, SEM_MIXED_FP32 = 1 } sem_precision;
+
+typedef struct {
+  int32_t nx, ny;          /* elements per direction                      */
+  const double *xb, *yb;   /* host arrays of nx+1 / ny+1 increasing breaks */
+  int32_t bc;              /* sem_bc; periodic needs nx, ny >= 3          */
+} sem_mesh;
+
+typedef struct {
+  int32_t rule;            /* sem_overlap_rule */
+  int32_t n_o;             /* used by SEM_NO_FIXED */
+} sem_overlap;
+
+typedef struct {
+  int32_t wf;              /* odd kappa, SEM_W_TOPHAT or SEM_W_ARITH */
+  /* Optional host arrays of nx+1 / ny+1 width scales in (0, 1], one per grid
+   * line (interface); the transition width at that interface is
+   * alpha * delta_o.  NULL means 1 everywhere (the paper's weights). */
+  const double *alpha_x, *alpha_y;
+} sem_weights;
+
+/* Build all levels, operators, fast-diagonalisation factors, weights,
+ * transfer matrices and the coarse solver (Sections 2-3; Section 4 for
+ * variable nu).  nu: host array of the finest level's nodal diffusivity
+ * (layout of level L), or NULL for the Poisson problem.  stream: a
+ * hipStream_t (NULL = default stream).  On success *out receives the handle.
+ * Errors: SEM_EINVAL (p < 1, n_o out of range, periodic with fewer than 3
+ * elements, NULL pointers), SEM_EDOM (breaks not increasing, nu <= 0),
+ * SEM_EUNSUP (subdomain width p+1+2 n_o above 48, p above 32),
+ * SEM_ENOMEM, SEM_EHIP. */
+sem_status sem_setup(const sem_mesh *mesh, int32_t p, const sem_overlap *overlap,
+                     const sem_weights *weights, const double *nu, int32_t precision,
+                     void *stream, sem_handle *out);
+sem_status sem_destroy(sem_handle h);
+
+/* Number of levels L+1 and, per level l (0 = coarsest, L = finest), the
+ * order p_l, the overlap n_o,l (0 on level 0) and the node-array shape. */
+sem_status sem_num_levels(sem_handle h, int32_t *nlevels);
+sem_status sem_level_info(sem_handle h, int32_t level, int32_t *p_l, int32_t *n_o,
+                          int64_t *rows, int64_t *cols);
+/* Host copies of the node coordinates of a level (cols x-values, rows
+ * y-values), for evaluating analytic data at the nodes. */
+sem_status sem_node_coords(sem_handle h, int32_t level, double *x, double *y);
+
+/* b = (M_y (x) M_x) f on level L: the right-hand side of A u = b for nodal
+ * source values f (Section 2).  Device arrays. */
+sem_status sem_mass(sem_handle h, const double *f_nodal, double *b);
+
+/* r = f - A_l u  (Section 3.1, residual form; A_l = B(nu_l) for variable nu).
+ * f may be NULL, then r = A_l u.  Device arrays of level `level`. */
+sem_status sem_residual(sem_handle h, int32_t level, const double *u, const double *f,
+                        double *r);
+
+/* n_it sweeps of the weighted additive Schwarz method (Algorithm 2) on level
+ * `level` >= 1: r = f - A u, then u += sum_s R_s^T W A_ss^{-1} R_s r with
+ * A_ss^{-1} by fast diagonalisation (scaled by 1/nu_bar_s for variable nu).
+ * u is updated in place. */
+sem_status sem_schwarz_smooth(sem_handle h, int32_t level, double *u, const double *f,
+                              int32_t n_it);
+
+/* f_c = I_l^T r_f (residual restriction, level l -> l-1) and
+ * u_f += I_l u_c (correction prolongation, l-1 -> l), Section 3.2. */
+sem_status sem_restrict(sem_handle h, int32_t level, const double *r_fine, double *f_coarse);
+sem_status sem_prolong_add(sem_handle h, int32_t level, const double *u_coarse,
+                           double *u_fine);
+
+/* u_0 = A_0^+ f_0 on level 0 (Algorithm 3, coarse grid solution); for a
+ * singular periodic A_0 the right side is projected onto the range and the
+ * zero-mean solution is returned. */
+sem_status sem_coarse_solve(sem_handle h, const double *f0, double *u0);
+
+/* One multigrid V-cycle (Algorithm 3) on the finest level: u updated in
+ * place.  ns1, ns2: host arrays of L+1 pre/post smoothing counts indexed by
+ * level (entry 0 unused); NULL gives MG(1,0). */
+sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *ns1,
+                      const int32_t *ns2);
+
+/* Inexact multigrid-preconditioned CG (Algorithm 4) until
+ * ||r||_2 <= rtol ||r_0||_2 or imax iterations.  Synchronises the stream
+ * once per iteration for the stopping test.  iters: iterations done;
+ * res_hist: optional host array of imax+1 residual norms.  Returns
+ * SEM_ENOCONV when imax is reached (u holds the last iterate). */
+sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax, double rtol,
+                         const int32_t *ns1, const int32_t *ns2, int32_t *iters,
+                         double *res_hist);
+
+/* Euclidean norm of the unknowns of a level-L array (synchronises). */
+sem_status sem_norm(sem_handle h, const double *x, double *out);
+
+const char *sem_strerror(sem_status s);
+const char *sem_last_error(sem_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

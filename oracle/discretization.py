@@ -48,6 +48,8 @@ class Axis:
         x = np.zeros(self.N)
         for e in range(self.n):
             for a in range(self.p + 1):
+                if self.bc == PERIODIC and e * self.p + a == self.N:
+                    continue        # the wrapped end node is node 0, at breaks[0]
                 x[self.node_index(e, a)] = self.breaks[e] + 0.5 * self.h[e] * (self.xi[a] + 1.0)
         return x
 

@@ -1,0 +1,1035 @@
+// C-ABI of the SEM Schwarz / p-multigrid solver: set-up of all levels and the
+// host-driven V-cycle (Algorithm 3) and MGCG (Algorithm 4) loops.  Every
+// arithmetic step on vectors runs in the HIP kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "host_math.h"
+#include "kernels.h"
+
+using namespace sem;
+
+namespace {
+
+struct Fail {
+  sem_status s;
+  std::string msg;
+};
+
+#define HIP_OK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      throw Fail{SEM_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+// Device buffer owned by the handle.
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = n;
+    if (n == 0) return;
+    if (hipMalloc(&p, n) != hipSuccess) throw Fail{SEM_ENOMEM, "hipMalloc failed"};
+  }
+  template <typename T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename T>
+T *upload(std::vector<std::unique_ptr<DBuf>> &pool, const std::vector<double> &h) {
+  pool.emplace_back(new DBuf());
+  DBuf &b = *pool.back();
+  b.alloc(h.size() * sizeof(T));
+  if (h.empty()) return nullptr;
+  std::vector<T> tmp(h.begin(), h.end());
+  HIP_OK(hipMemcpy(b.p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return b.as<T>();
+}
+
+template <typename T>
+T *dalloc(std::vector<std::unique_ptr<DBuf>> &pool, size_t n) {
+  pool.emplace_back(new DBuf());
+  pool.back()->alloc(n * sizeof(T));
+  return pool.back()->as<T>();
+}
+
+// Tables of one level in one precision.
+template <typename T>
+struct Tables {
+  T *Lhat = nullptr, *D = nullptr, *w = nullptr;
+  T *sx = nullptr, *sy = nullptr, *mx = nullptr, *my = nullptr;
+  T *Sx = nullptr, *SxT = nullptr, *SyW = nullptr, *SyT = nullptr, *dinv = nullptr;
+  T *wx = nullptr, *nuinv = nullptr, *nu = nullptr, *DT = nullptr;
+  T *E = nullptr;  // prolongation from level l-1
+};
+
+// Host description of the subdomain types along one direction.
+struct DirFdm {
+  int ntypes = 0;
+  std::vector<int> type_of;       // per element
+  std::vector<double> S, ST, SW, lam;  // per type m*m (S, S^T, diag(w) S), m
+  std::vector<double> wts;        // per element m
+};
+
+struct Level {
+  int p = 1, n_o = 0, m = 0;
+  Grid g{};
+  std::vector<double> xc, yc;     // node coordinates
+  std::vector<double> nu_host;    // nodal nu (variable coefficient)
+  Tables<double> td;
+  Tables<float> tf;
+  FdmTask *tasks = nullptr;
+  int ntasks = 0, ntx = 0, nty = 0;
+  // level vectors (FP64 and FP32)
+  double *u = nullptr, *f = nullptr, *r = nullptr, *t = nullptr;
+  float *uf = nullptr, *ff = nullptr, *rf = nullptr, *tf_ = nullptr;
+  long n() const { return (long)g.rows * g.cols; }
+};
+
+}  // namespace
+
+struct sem_ctx {
+  hipStream_t stream = nullptr;
+  int precision = SEM_FP64;
+  int bc = SEM_BC_DIRICHLET;
+  bool varnu = false;
+  std::vector<Level> lev;
+  std::vector<std::unique_ptr<DBuf>> pool;
+  // coarse solver
+  int cnx = 0, cny = 0;           // unknowns per direction on level 0
+  long coff = 0;                  // offset of the unknown block in the node array
+  double *cSx = nullptr, *cSy = nullptr, *cDinv = nullptr, *cT1 = nullptr, *cT2 = nullptr;
+  double *cMinv = nullptr;        // dense inverse (variable nu)
+  double *cf = nullptr;           // projected copy of f0 (periodic)
+  double *cu64 = nullptr, *cf64 = nullptr;  // FP64 coarse vectors for the FP32 cycle
+  // PCG / reductions
+  double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr, *pro = nullptr;
+  double *partial = nullptr, *scal = nullptr;  // scal: device scalars
+  std::string err;
+};
+
+namespace {
+
+int level_overlap(int rule, int n_o, int pl) {
+  int v;
+  switch (rule) {
+    case SEM_NO_FIXED: v = n_o; break;
+    case SEM_NO_CEIL_P8: v = (pl + 7) / 8; break;
+    case SEM_NO_FLOOR_P8: v = pl / 8; break;
+    case SEM_NO_CEIL_P2: v = (pl + 1) / 2; break;
+    default: throw Fail{SEM_EINVAL, "unknown overlap rule"};
+  }
+  return std::max(0, std::min(v, pl - 1));
+}
+
+// Subdomain types, factors and weights along one direction (Section 3.1).
+DirFdm build_direction(const std::vector<double> &br, int p, int n_o, int periodic, int wf,
+                       const double *alpha) {
+  const int n = (int)br.size() - 1;
+  const int m = p + 1 + 2 * n_o;
+  const int N = periodic ? n * p : n * p + 1;
+  Vec xi, w;
+  gll_rule(p, xi, w);
+  Mat Lh = ref_stiffness(p);
+  DirFdm out;
+  out.type_of.assign(n, -1);
+  out.wts.assign((size_t)n * m, 0.0);
+  std::vector<std::vector<double>> sigL, sigM;  // signatures of known types
+  std::vector<std::vector<char>> sigV;
+  std::vector<std::vector<double>> sigW;
+  // multiplicity of every node over the 1-D subdomains (arithmetic weights)
+  std::vector<int> count(N, 0);
+  auto glob = [&](int e, int k, bool &valid) {
+    int g = e * p - n_o + k;
+    if (periodic) {
+      g = ((g % N) + N) % N;
+      valid = true;
+    } else {
+      valid = g >= 1 && g <= N - 2;
+    }
+    return g;
+  };
+  for (int e = 0; e < n; ++e)
+    for (int k = 0; k < m; ++k) {
+      bool v;
+      int g = glob(e, k, v);
+      if (v) count[g]++;
+    }
+  const double delta = xi[n_o + 1] + 1.0;
+  for (int e = 0; e < n; ++e) {
+    // restricted 1-D stiffness and mass on the window [e p - n_o, (e+1) p + n_o]
+    Mat Ls(m, m);
+    Vec Ms(m, 0.0);
+    std::vector<char> valid(m);
+    for (int k = 0; k < m; ++k) {
+      bool v;
+      glob(e, k, v);
+      valid[k] = v;
+    }
+    for (int d = -1; d <= 1; ++d) {
+      int E = e + d;
+      if (!periodic && (E < 0 || E >= n)) continue;
+      int Ew = periodic ? (E + n) % n : E;
+      const double h = br[Ew + 1] - br[Ew];
+      for (int a = 0; a <= p; ++a) {
+        const int ka = d * p + a + n_o;
+        if (ka < 0 || ka >= m) continue;
+        Ms[ka] += 0.5 * h * w[a];
+        for (int b = 0; b <= p; ++b) {
+          const int kb = d * p + b + n_o;
+          if (kb < 0 || kb >= m) continue;
+          Ls(ka, kb) += (2.0 / h) * Lh(a, b);
+        }
+      }
+    }
+    // weights of this subdomain (eq. weight function, or counting for w_a)
+    std::vector<double> we(m, 0.0);
+    {
+      const double al = alpha ? alpha[e] : 1.0;
+      const double ar = alpha ? alpha[periodic && e == n - 1 ? 0 : e + 1] : 1.0;
+      for (int k = 0; k < m; ++k) {
+        bool v;
+        int g = glob(e, k, v);
+        if (!v) continue;
+        if (wf == SEM_W_ARITH) {
+          we[k] = 1.0 / count[g];
+        } else {
+          const int t = k - n_o;
+          const double x = t < 0 ? xi[p + t] - 2.0 : (t > p ? xi[t - p] + 2.0 : xi[t]);
+          const bool satl = !periodic && e == 0, satr = !periodic && e == n - 1;
+          we[k] = weight_fn(wf, x, al * delta, ar * delta, satl, satr);
+        }
+      }
+    }
+    // signature and type lookup (equal matrices to 1e-12, equal weights)
+    std::vector<double> sl, sm;
+    for (int i = 0; i < m; ++i) {
+      sm.push_back(valid[i] ? Ms[i] : 0.0);
+      for (int j = 0; j < m; ++j) sl.push_back(valid[i] && valid[j] ? Ls(i, j) : 0.0);
+    }
+    int type = -1;
+    for (int t = 0; t < out.ntypes && type < 0; ++t) {
+      if (sigV[t] != valid) continue;
+      double dmax = 0.0, smax = 0.0;
+      for (size_t i = 0; i < sl.size(); ++i) {
+        dmax = std::max(dmax, std::fabs(sl[i] - sigL[t][i]));
+        smax = std::max(smax, std::fabs(sl[i]));
+      }
+      for (size_t i = 0; i < sm.size(); ++i) {
+        dmax = std::max(dmax, std::fabs(sm[i] - sigM[t][i]) * smax / (std::fabs(sm[i]) + 1e-300));
+      }
+      double wmax = 0.0;
+      for (int i = 0; i < m; ++i) wmax = std::max(wmax, std::fabs(we[i] - sigW[t][i]));
+      if (dmax <= 1e-12 * smax && wmax <= 1e-15) type = t;
+    }
+    if (type < 0) {
+      type = out.ntypes++;
+      sigL.push_back(sl);
+      sigM.push_back(sm);
+      sigV.push_back(valid);
+      sigW.push_back(we);
+      // generalised eigenproblem on the valid positions, padded with identity
+      std::vector<int> vi, ii;
+      for (int k = 0; k < m; ++k) (valid[k] ? vi : ii).push_back(k);
+      const int nv = (int)vi.size();
+      Mat L(nv, nv);
+      Vec M(nv);
+      for (int a = 0; a < nv; ++a) {
+        M[a] = Ms[vi[a]];
+        for (int b = 0; b < nv; ++b) L(a, b) = Ls(vi[a], vi[b]);
+      }
+      Vec lam;
+      Mat S;
+      gen_eig_diag(L, M, lam, S);
+      std::vector<double> Sp((size_t)m * m, 0.0), lp(m, 1.0);
+      for (int a = 0; a < nv; ++a) {
+        lp[a] = lam[a];
+        for (int c = 0; c < nv; ++c) Sp[(size_t)vi[a] * m + c] = S(a, c);
+      }
+      for (size_t t = 0; t < ii.size(); ++t) Sp[(size_t)ii[t] * m + nv + t] = 1.0;
+      out.S.insert(out.S.end(), Sp.begin(), Sp.end());
+      for (int a = 0; a < m; ++a)
+        for (int c = 0; c < m; ++c) out.ST.push_back(Sp[(size_t)c * m + a]);
+      for (int a = 0; a < m; ++a)
+        for (int c = 0; c < m; ++c) out.SW.push_back(we[a] * Sp[(size_t)a * m + c]);
+      out.lam.insert(out.lam.end(), lp.begin(), lp.end());
+    }
+    out.type_of[e] = type;
+    std::copy(we.begin(), we.end(), out.wts.begin() + (size_t)e * m);
+  }
+  return out;
+}
+
+template <typename T>
+void upload_tables(sem_ctx *h, Level &L, Tables<T> &t, const std::vector<double> &Lhat,
+                   const std::vector<double> &D, const std::vector<double> &DT,
+                   const std::vector<double> &w,
+                   const std::vector<double> &sx, const std::vector<double> &sy,
+                   const std::vector<double> &mx, const std::vector<double> &my,
+                   const DirFdm *fx, const DirFdm *fy, const std::vector<double> &dinv,
+                   const std::vector<double> &nuinv, const std::vector<double> &E) {
+  auto &P = h->pool;
+  t.Lhat = upload<T>(P, Lhat);
+  t.D = upload<T>(P, D);
+  t.DT = upload<T>(P, DT);
+  t.w = upload<T>(P, w);
+  t.sx = upload<T>(P, sx);
+  t.sy = upload<T>(P, sy);
+  t.mx = upload<T>(P, mx);
+  t.my = upload<T>(P, my);
+  if (fx) {
+    t.Sx = upload<T>(P, fx->S);
+    t.SxT = upload<T>(P, fx->ST);
+    t.SyW = upload<T>(P, fy->SW);
+    t.SyT = upload<T>(P, fy->ST);
+    t.dinv = upload<T>(P, dinv);
+    t.wx = upload<T>(P, fx->wts);
+  }
+  if (!nuinv.empty()) t.nuinv = upload<T>(P, nuinv);
+  if (!L.nu_host.empty()) t.nu = upload<T>(P, L.nu_host);
+  if (!E.empty()) t.E = upload<T>(P, E);
+}
+
+std::vector<double> flat(const Mat &M) { return M.a; }
+
+// Dense matrix of B(nu) (or A) on the unknowns of a p = 1 level, assembled
+// from 4x4 element matrices by GLL quadrature (Section 4).
+Mat coarse_dense(const Level &L, const std::vector<double> &xb, const std::vector<double> &yb) {
+  const Grid &g = L.g;
+  const int per = g.periodic;
+  const int nux = per ? g.cols : g.cols - 2, nuy = per ? g.rows : g.rows - 2;
+  const int n = nux * nuy;
+  Mat B(n, n);
+  auto num = [&](int row, int col) -> int {
+    if (per) return (row % g.rows) * nux + (col % g.cols);
+    if (row < 1 || row > g.rows - 2 || col < 1 || col > g.cols - 2) return -1;
+    return (row - 1) * nux + (col - 1);
+  };
+  // p = 1: GLL points -1, 1, weights 1, 1; D = [[-1/2, 1/2], [-1/2, 1/2]]
+  const double Dm[2][2] = {{-0.5, 0.5}, {-0.5, 0.5}};
+  for (int ey = 0; ey < g.ny; ++ey)
+    for (int ex = 0; ex < g.nx; ++ex) {
+      const double hx = xb[ex + 1] - xb[ex], hy = yb[ey + 1] - yb[ey];
+      double nu[2][2];
+      int id[2][2];
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int row = (ey + b) % (per ? g.rows : 1 << 30), col = (ex + a) % (per ? g.cols : 1 << 30);
+          nu[b][a] = L.nu_host.empty() ? 1.0 : L.nu_host[(size_t)row * g.cols + col];
+          id[b][a] = num(ey + b, ex + a);
+        }
+      // element matrix K[(b,a),(d,c)]
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          if (id[b][a] < 0) continue;
+          for (int d = 0; d < 2; ++d)
+            for (int c = 0; c < 2; ++c) {
+              if (id[d][c] < 0) continue;
+              // x part: (hy/hx) sum_q w_q w_b nu D[q][a] D[q][c] delta_bd
+              double v = 0.0;
+              if (b == d)
+                for (int q = 0; q < 2; ++q) v += (hy / hx) * nu[b][q] * Dm[q][a] * Dm[q][c];
+              if (a == c)
+                for (int q = 0; q < 2; ++q) v += (hx / hy) * nu[q][a] * Dm[q][b] * Dm[q][d];
+              B(id[b][a], id[d][c]) += v;
+            }
+        }
+    }
+  return B;
+}
+
+void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
+                const sem_weights *wts, const double *nu) {
+  if (!mesh || !ov || !wts || !mesh->xb || !mesh->yb) throw Fail{SEM_EINVAL, "null argument"};
+  if (p < 1) throw Fail{SEM_EINVAL, "p must be >= 1"};
+  if (p > kMaxOrder) throw Fail{SEM_EUNSUP, "p above 32"};
+  const int nx = mesh->nx, ny = mesh->ny, per = mesh->bc == SEM_BC_PERIODIC;
+  if (nx < 1 || ny < 1 || nx > 65535 || ny > 65535) throw Fail{SEM_EINVAL, "bad element counts"};
+  if (mesh->bc != SEM_BC_DIRICHLET && !per) throw Fail{SEM_EINVAL, "bad boundary condition"};
+  if (per && (nx < 3 || ny < 3)) throw Fail{SEM_EINVAL, "periodic needs at least 3 elements"};
+  if (ov->rule == SEM_NO_FIXED && ov->n_o < 0) throw Fail{SEM_EINVAL, "n_o < 0"};
+  if (!(wts->wf == SEM_W_TOPHAT || wts->wf == SEM_W_ARITH || (wts->wf >= 1 && wts->wf % 2 == 1)))
+    throw Fail{SEM_EINVAL, "weight function must be odd kappa, top hat or arithmetic"};
+  std::vector<double> xb(mesh->xb, mesh->xb + nx + 1), yb(mesh->yb, mesh->yb + ny + 1);
+  for (int i = 0; i < nx; ++i)
+    if (!(xb[i + 1] > xb[i])) throw Fail{SEM_EDOM, "x breaks not increasing"};
+  for (int i = 0; i < ny; ++i)
+    if (!(yb[i + 1] > yb[i])) throw Fail{SEM_EDOM, "y breaks not increasing"};
+  for (const double *a : {wts->alpha_x, wts->alpha_y}) {
+    if (!a) continue;
+    const int n = (a == wts->alpha_x ? nx : ny) + 1;
+    for (int i = 0; i < n; ++i)
+      if (!(a[i] > 0.0 && a[i] <= 1.0)) throw Fail{SEM_EINVAL, "width scales must lie in (0, 1]"};
+  }
+  h->bc = mesh->bc;
+  h->varnu = nu != nullptr;
+  // level orders p_L = p, p_{l-1} = ceil(p_l / 2)
+  std::vector<int> orders{p};
+  while (orders.back() > 1) orders.push_back((orders.back() + 1) / 2);
+  std::reverse(orders.begin(), orders.end());
+  const int L = (int)orders.size() - 1;
+  h->lev.resize(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    Level &lv = h->lev[l];
+    lv.p = orders[l];
+    lv.n_o = l == 0 ? 0 : level_overlap(ov->rule, ov->n_o, lv.p);
+    lv.m = lv.p + 1 + 2 * lv.n_o;
+    if (l > 0 && lv.m > kMaxTile) throw Fail{SEM_EUNSUP, "subdomain width p+1+2n_o above 48"};
+    lv.g = Grid{nx, ny, lv.p, per ? ny * lv.p : ny * lv.p + 1, per ? nx * lv.p : nx * lv.p + 1, per};
+    Vec xi, w;
+    gll_rule(lv.p, xi, w);
+    lv.xc.assign(lv.g.cols, 0.0);
+    lv.yc.assign(lv.g.rows, 0.0);
+    for (int e = 0; e < nx; ++e)
+      for (int a = 0; a <= lv.p; ++a) {
+        int c = e * lv.p + a;
+        if (per && c == lv.g.cols) continue;
+        lv.xc[c] = xb[e] + 0.5 * (xb[e + 1] - xb[e]) * (xi[a] + 1.0);
+      }
+    for (int e = 0; e < ny; ++e)
+      for (int a = 0; a <= lv.p; ++a) {
+        int r = e * lv.p + a;
+        if (per && r == lv.g.rows) continue;
+        lv.yc[r] = yb[e] + 0.5 * (yb[e + 1] - yb[e]) * (xi[a] + 1.0);
+      }
+  }
+  // variable coefficient: nodal nu on every level, element means on the top
+  std::vector<double> nubar;
+  if (nu) {
+    Level &top = h->lev[L];
+    top.nu_host.assign(nu, nu + top.n());
+    for (double v : top.nu_host)
+      if (!(v > 0.0) || !std::isfinite(v)) throw Fail{SEM_EDOM, "nu must be positive and finite"};
+    Vec xiL, wL;
+    gll_rule(top.p, xiL, wL);
+    nubar.assign((size_t)nx * ny, 0.0);
+    for (int ey = 0; ey < ny; ++ey)
+      for (int ex = 0; ex < nx; ++ex) {
+        double s = 0.0;
+        for (int b = 0; b <= top.p; ++b)
+          for (int a = 0; a <= top.p; ++a) {
+            int row = (ey * top.p + b) % top.g.rows, col = (ex * top.p + a) % top.g.cols;
+            if (!per) { row = ey * top.p + b; col = ex * top.p + a; }
+            s += wL[a] * wL[b] * top.nu_host[(size_t)row * top.g.cols + col];
+          }
+        nubar[(size_t)ey * nx + ex] = s / 4.0;
+      }
+    for (int l = 0; l < L; ++l) {
+      Level &lv = h->lev[l];
+      Vec xi, w;
+      gll_rule(lv.p, xi, w);
+      Mat E = lagrange_eval(xiL, xi);  // (p_l+1) x (p_L+1)
+      lv.nu_host.assign(lv.n(), 0.0);
+      for (int ey = 0; ey < ny; ++ey)
+        for (int ex = 0; ex < nx; ++ex)
+          for (int b = 0; b <= lv.p; ++b)
+            for (int a = 0; a <= lv.p; ++a) {
+              double s = 0.0;
+              for (int d = 0; d <= top.p; ++d) {
+                double t = 0.0;
+                for (int c = 0; c <= top.p; ++c) {
+                  int row = ey * top.p + d, col = ex * top.p + c;
+                  if (per) { row %= top.g.rows; col %= top.g.cols; }
+                  t += E(a, c) * top.nu_host[(size_t)row * top.g.cols + col];
+                }
+                s += E(b, d) * t;
+              }
+              int row = ey * lv.p + b, col = ex * lv.p + a;
+              if (per) { row %= lv.g.rows; col %= lv.g.cols; }
+              lv.nu_host[(size_t)row * lv.g.cols + col] = s;
+            }
+    }
+  }
+  std::vector<double> nuinv;
+  for (double v : nubar) nuinv.push_back(1.0 / v);
+  const bool mixed = h->precision == SEM_MIXED_FP32;
+  // per-level tables
+  for (int l = 0; l <= L; ++l) {
+    Level &lv = h->lev[l];
+    Vec xi, w;
+    gll_rule(lv.p, xi, w);
+    Mat D = lagrange_derivative(xi);
+    Mat Lh = ref_stiffness(lv.p);
+    std::vector<double> sx(nx), sy(ny), mx(nx), my(ny);
+    for (int e = 0; e < nx; ++e) { sx[e] = 2.0 / (xb[e + 1] - xb[e]); mx[e] = 0.5 * (xb[e + 1] - xb[e]); }
+    for (int e = 0; e < ny; ++e) { sy[e] = 2.0 / (yb[e + 1] - yb[e]); my[e] = 0.5 * (yb[e + 1] - yb[e]); }
+    std::vector<double> E;
+    if (l > 0) {
+      Vec xic, wc;
+      gll_rule(h->lev[l - 1].p, xic, wc);
+      E = flat(lagrange_eval(xic, xi));
+    }
+    DirFdm fx, fy;
+    std::vector<double> dinv;
+    if (l > 0) {
+      fx = build_direction(xb, lv.p, lv.n_o, per, wts->wf, wts->alpha_x);
+      fy = build_direction(yb, lv.p, lv.n_o, per, wts->wf, wts->alpha_y);
+      const int m = lv.m;
+      lv.ntx = fx.ntypes;
+      lv.nty = fy.ntypes;
+      dinv.resize((size_t)fy.ntypes * fx.ntypes * m * m);
+      for (int ty = 0; ty < fy.ntypes; ++ty)
+        for (int tx = 0; tx < fx.ntypes; ++tx)
+          for (int a = 0; a < m; ++a)
+            for (int c = 0; c < m; ++c)
+              dinv[(((size_t)ty * fx.ntypes + tx) * m + a) * m + c] =
+                  1.0 / (fy.lam[(size_t)ty * m + a] + fx.lam[(size_t)tx * m + c]);
+      // work items: elements grouped by (ty, tx), EPW = 64/m per wavefront
+      const int epw = std::min(64 / m, kTaskSlots);
+      std::vector<FdmTask> tasks;
+      for (int ty = 0; ty < fy.ntypes; ++ty)
+        for (int tx = 0; tx < fx.ntypes; ++tx) {
+          FdmTask cur{};
+          cur.ty = ty;
+          cur.tx = tx;
+          for (int ey = 0; ey < ny; ++ey) {
+            if (fy.type_of[ey] != ty) continue;
+            for (int ex = 0; ex < nx; ++ex) {
+              if (fx.type_of[ex] != tx) continue;
+              cur.elem[cur.count++] = (ey << 16) | ex;
+              if (cur.count == epw) {
+                tasks.push_back(cur);
+                cur.count = 0;
+              }
+            }
+          }
+          if (cur.count) tasks.push_back(cur);
+        }
+      lv.ntasks = (int)tasks.size();
+      h->pool.emplace_back(new DBuf());
+      h->pool.back()->alloc(tasks.size() * sizeof(FdmTask));
+      lv.tasks = h->pool.back()->as<FdmTask>();
+      HIP_OK(hipMemcpy(lv.tasks, tasks.data(), tasks.size() * sizeof(FdmTask), hipMemcpyHostToDevice));
+    }
+    const std::vector<double> &ninv = (l > 0) ? nuinv : std::vector<double>();
+    std::vector<double> DTv((size_t)(lv.p + 1) * (lv.p + 1));
+    for (int a = 0; a <= lv.p; ++a)
+      for (int b = 0; b <= lv.p; ++b) DTv[(size_t)a * (lv.p + 1) + b] = D(b, a);
+    upload_tables<double>(h, lv, lv.td, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, l > 0 ? &fx : nullptr,
+                          l > 0 ? &fy : nullptr, dinv, ninv, E);
+    if (mixed)
+      upload_tables<float>(h, lv, lv.tf, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, l > 0 ? &fx : nullptr,
+                           l > 0 ? &fy : nullptr, dinv, ninv, E);
+    // vectors
+    const long n = lv.n();
+    long tn = 0;
+    if (l > 0) {
+      const Level &c = h->lev[l - 1];
+      tn = std::max((long)lv.g.rows * c.g.cols, (long)c.g.rows * lv.g.cols);
+    }
+    if (l < L) {
+      lv.u = dalloc<double>(h->pool, n);
+      lv.f = dalloc<double>(h->pool, n);
+    }
+    lv.r = dalloc<double>(h->pool, n);
+    if (tn) lv.t = dalloc<double>(h->pool, tn);
+    if (mixed) {
+      lv.uf = dalloc<float>(h->pool, n);
+      lv.ff = dalloc<float>(h->pool, n);
+      lv.rf = dalloc<float>(h->pool, n);
+      if (tn) lv.tf_ = dalloc<float>(h->pool, tn);
+    }
+  }
+  // coarse solver (level 0, p = 1)
+  {
+    Level &c = h->lev[0];
+    h->cnx = per ? c.g.cols : c.g.cols - 2;
+    h->cny = per ? c.g.rows : c.g.rows - 2;
+    h->coff = per ? 0 : (long)c.g.cols + 1;
+    if (h->varnu) {
+      const long n = (long)h->cnx * h->cny;
+      if (n > 6000) throw Fail{SEM_EUNSUP, "coarse grid too large for the dense variable-nu solve"};
+      Mat B = coarse_dense(c, xb, yb);
+      if (per) {
+        double tr = 0.0;
+        for (long i = 0; i < n; ++i) tr += B(i, i);
+        const double s = tr / ((double)n * n);
+        for (long i = 0; i < n; ++i)
+          for (long j = 0; j < n; ++j) B(i, j) += s;
+      }
+      if (!spd_inverse(B)) throw Fail{SEM_EINVAL, "coarse operator not positive definite"};
+      h->cMinv = upload<double>(h->pool, B.a);
+    } else {
+      // global fast diagonalisation of A_0 = M_y (x) L_x + L_y (x) M_x
+      auto dir = [&](const std::vector<double> &br, int n_un, std::vector<double> &S,
+                     std::vector<double> &lam) {
+        const int n = (int)br.size() - 1;
+        const int N = per ? n : n + 1;
+        Mat Lg(N, N);
+        Vec Mg(N, 0.0);
+        for (int e = 0; e < n; ++e) {
+          const double hh = br[e + 1] - br[e];
+          const int i0 = e, i1 = per ? (e + 1) % N : e + 1;
+          Mg[i0] += 0.5 * hh;
+          Mg[i1] += 0.5 * hh;
+          Lg(i0, i0) += 1.0 / hh;
+          Lg(i1, i1) += 1.0 / hh;
+          Lg(i0, i1) -= 1.0 / hh;
+          Lg(i1, i0) -= 1.0 / hh;
+        }
+        const int o = per ? 0 : 1;
+        Mat Lu(n_un, n_un);
+        Vec Mu(n_un);
+        for (int i = 0; i < n_un; ++i) {
+          Mu[i] = Mg[i + o];
+          for (int j = 0; j < n_un; ++j) Lu(i, j) = Lg(i + o, j + o);
+        }
+        Mat Sm;
+        gen_eig_diag(Lu, Mu, lam, Sm);
+        S = Sm.a;
+      };
+      if (std::max(h->cnx, h->cny) > 2048)
+        throw Fail{SEM_EUNSUP, "coarse grid above 2048 unknowns per direction"};
+      std::vector<double> Sx, Sy, lx, ly;
+      dir(xb, h->cnx, Sx, lx);
+      dir(yb, h->cny, Sy, ly);
+      std::vector<double> Dv((size_t)h->cny * h->cnx);
+      const double lmax = lx.back() + ly.back();
+      for (int j = 0; j < h->cny; ++j)
+        for (int i = 0; i < h->cnx; ++i) {
+          const double s = ly[j] + lx[i];
+          Dv[(size_t)j * h->cnx + i] = (per && std::fabs(s) < 1e-12 * lmax) ? 0.0 : 1.0 / s;
+        }
+      h->cSx = upload<double>(h->pool, Sx);
+      h->cSy = upload<double>(h->pool, Sy);
+      h->cDinv = upload<double>(h->pool, Dv);
+      h->cT1 = dalloc<double>(h->pool, (size_t)h->cnx * h->cny);
+      h->cT2 = dalloc<double>(h->pool, (size_t)h->cnx * h->cny);
+    }
+    h->cf = dalloc<double>(h->pool, c.n());
+    if (mixed) {
+      h->cu64 = dalloc<double>(h->pool, c.n());
+      h->cf64 = dalloc<double>(h->pool, c.n());
+    }
+  }
+  // PCG vectors
+  {
+    const long n = h->lev[L].n();
+    h->pr = dalloc<double>(h->pool, n);
+    h->pp = dalloc<double>(h->pool, n);
+    h->pq = dalloc<double>(h->pool, n);
+    h->pz = dalloc<double>(h->pool, n);
+    h->pro = dalloc<double>(h->pool, n);
+    h->partial = dalloc<double>(h->pool, 2 * kRedBlocks);
+    h->scal = dalloc<double>(h->pool, 16);
+  }
+  HIP_OK(hipDeviceSynchronize());
+}
+
+// ---------------------------------------------------------------------------
+// Level operations (templated on the working precision)
+// ---------------------------------------------------------------------------
+template <typename T>
+Tables<T> &tabs(Level &L);
+template <>
+Tables<double> &tabs<double>(Level &L) { return L.td; }
+template <>
+Tables<float> &tabs<float>(Level &L) { return L.tf; }
+
+template <typename T>
+void residual(sem_ctx *h, int l, const T *u, const T *f, T *out) {
+  Level &L = h->lev[l];
+  Tables<T> &t = tabs<T>(L);
+  ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu};
+  launch_residual<T>(a, h->stream);
+}
+
+template <typename T>
+void fdm(sem_ctx *h, int l, const T *r, T *u) {
+  Level &L = h->lev[l];
+  Tables<T> &t = tabs<T>(L);
+  FdmArgs<T> a{L.g, L.n_o, L.m, L.tasks, L.ntasks, r, u, t.Sx, t.SxT, t.SyW, t.SyT, t.dinv, L.ntx,
+               t.wx, t.nuinv};
+  launch_fdm<T>(a, h->stream);
+}
+
+// n_it sweeps of Algorithm 2; if u_is_zero the first residual is f itself.
+template <typename T>
+void smooth(sem_ctx *h, int l, T *u, const T *f, T *rbuf, int n_it, bool u_is_zero) {
+  for (int it = 0; it < n_it; ++it) {
+    const T *r = f;
+    if (!(it == 0 && u_is_zero)) {
+      residual<T>(h, l, u, f, rbuf);
+      r = rbuf;
+    }
+    fdm<T>(h, l, r, u);
+  }
+}
+
+template <typename T>
+void restrict_(sem_ctx *h, int l, const T *rf, T *fc, T *tmp) {
+  Level &F = h->lev[l], &C = h->lev[l - 1];
+  const Tables<T> &t = tabs<T>(F);
+  // x pass: fine rows x coarse cols, then y pass: coarse rows x coarse cols
+  launch_transfer<T>(0, 1, 0, rf, F.g.rows, F.g.cols, tmp, F.g.rows, C.g.cols, F.g.nx, F.p, C.p,
+                     F.g.periodic, t.E, h->stream);
+  launch_transfer<T>(1, 1, 0, tmp, F.g.rows, C.g.cols, fc, C.g.rows, C.g.cols, F.g.ny, F.p, C.p,
+                     F.g.periodic, t.E, h->stream);
+}
+
+template <typename T>
+void prolong_add(sem_ctx *h, int l, const T *uc, T *uf, T *tmp) {
+  Level &F = h->lev[l], &C = h->lev[l - 1];
+  const Tables<T> &t = tabs<T>(F);
+  launch_transfer<T>(0, 0, 0, uc, C.g.rows, C.g.cols, tmp, C.g.rows, F.g.cols, F.g.nx, F.p, C.p,
+                     F.g.periodic, t.E, h->stream);
+  launch_transfer<T>(1, 0, 1, tmp, C.g.rows, F.g.cols, uf, F.g.rows, F.g.cols, F.g.ny, F.p, C.p,
+                     F.g.periodic, t.E, h->stream);
+}
+
+// u0 = A_0^+ f0 in FP64.
+void coarse_solve64(sem_ctx *h, const double *f0, double *u0) {
+  Level &c = h->lev[0];
+  hipStream_t s = h->stream;
+  const double *f = f0;
+  if (c.g.periodic) {
+    HIP_OK(hipMemcpyAsync(h->cf, f0, c.n() * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_sum(h->cf, c.n(), h->partial, h->scal + 8, s);
+    launch_sub_mean(c.g, h->cf, h->scal + 8, s);
+    f = h->cf;
+  }
+  launch_fill<double>(u0, c.n(), 0.0, s);
+  const int nx = h->cnx, ny = h->cny;
+  const long ld = c.g.cols;
+  if (nx == 0 || ny == 0) return;  // no coarse unknowns (one Dirichlet element)
+  if (h->cMinv) {
+    launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
+  } else {
+    // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T
+    launch_gemm(ny, nx, ny, h->cSy, 1, ny, f + h->coff, ld, 1, h->cT1, nx, nullptr, 0, s);
+    launch_gemm(ny, nx, nx, h->cT1, nx, 1, h->cSx, nx, 1, h->cT2, nx, h->cDinv, nx, s);
+    launch_gemm(ny, nx, ny, h->cSy, ny, 1, h->cT2, nx, 1, h->cT1, nx, nullptr, 0, s);
+    launch_gemm(ny, nx, nx, h->cT1, nx, 1, h->cSx, 1, nx, u0 + h->coff, ld, nullptr, 0, s);
+  }
+  if (c.g.periodic) {
+    launch_sum(u0, c.n(), h->partial, h->scal + 8, s);
+    launch_sub_mean(c.g, u0, h->scal + 8, s);
+  }
+}
+
+void coarse_solve(sem_ctx *h, const double *f0, double *u0) { coarse_solve64(h, f0, u0); }
+void coarse_solve(sem_ctx *h, const float *f0, float *u0) {
+  const long n = h->lev[0].n();
+  launch_convert<float, double>(f0, h->cf64, n, 1.0, h->stream);
+  coarse_solve64(h, h->cf64, h->cu64);
+  launch_convert<double, float>(h->cu64, u0, n, 1.0, h->stream);
+}
+
+template <typename T>
+struct LevelVecs {
+  static T *u(Level &L) { return L.u; }
+  static T *f(Level &L) { return L.f; }
+  static T *r(Level &L) { return L.r; }
+  static T *t(Level &L) { return L.t; }
+};
+template <>
+struct LevelVecs<float> {
+  static float *u(Level &L) { return L.uf; }
+  static float *f(Level &L) { return L.ff; }
+  static float *r(Level &L) { return L.rf; }
+  static float *t(Level &L) { return L.tf_; }
+};
+
+// Algorithm 3 on arrays of precision T.  uL/fL are the top-level arrays;
+// u_zero tells that uL is zero on entry.
+template <typename T>
+void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32_t *ns2,
+                 bool u_zero) {
+  using V = LevelVecs<T>;
+  const int L = (int)h->lev.size() - 1;
+  std::vector<T *> u(L + 1);
+  std::vector<const T *> f(L + 1);
+  u[L] = uL;
+  f[L] = fL;
+  for (int l = L; l >= 1; --l) {
+    Level &lv = h->lev[l];
+    const bool zero = (l < L) || u_zero;
+    if (l < L) {
+      u[l] = V::u(lv);
+      launch_fill<T>(u[l], lv.n(), T(0), h->stream);
+    }
+    const int n1 = ns1 ? ns1[l] : 1;
+    smooth<T>(h, l, u[l], f[l], V::r(lv), n1, zero);
+    const T *rr = f[l];
+    if (!(zero && n1 == 0)) {
+      residual<T>(h, l, u[l], f[l], V::r(lv));
+      rr = V::r(lv);
+    }
+    T *fc = V::f(h->lev[l - 1]);
+    restrict_<T>(h, l, rr, fc, V::t(lv));
+    f[l - 1] = fc;
+  }
+  // with a single level (p = 1) the cycle is the coarse solve on the caller's array
+  if (L > 0) u[0] = V::u(h->lev[0]);
+  coarse_solve(h, f[0], u[0]);
+  for (int l = 1; l <= L; ++l) {
+    Level &lv = h->lev[l];
+    if (l < L) u[l] = V::u(lv);
+    prolong_add<T>(h, l, u[l - 1], u[l], V::t(lv));
+    smooth<T>(h, l, u[l], f[l], V::r(lv), ns2 ? ns2[l] : 0, false);
+  }
+}
+
+// Preconditioner z = MG(0, r) in the handle's precision (FP64 in, FP64 out).
+void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, const int32_t *ns2) {
+  Level &top = h->lev.back();
+  const long n = top.n();
+  if (h->precision == SEM_MIXED_FP32) {
+    launch_convert<double, float>(r, top.ff, n, 1.0, h->stream);
+    launch_fill<float>(top.uf, n, 0.0f, h->stream);
+    vcycle_impl<float>(h, top.uf, top.ff, ns1, ns2, true);
+    launch_convert<float, double>(top.uf, z, n, 1.0, h->stream);
+  } else {
+    launch_fill<double>(z, n, 0.0, h->stream);
+    vcycle_impl<double>(h, z, r, ns1, ns2, true);
+  }
+}
+
+double read_scalar(sem_ctx *h, const double *d) {
+  double v;
+  HIP_OK(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C entry points
+// ---------------------------------------------------------------------------
+namespace {
+sem_status guard(sem_ctx *h, const std::function<void()> &fn) {
+  try {
+    fn();
+    if (h) {
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) throw Fail{SEM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+    }
+    return SEM_OK;
+  } catch (const Fail &f) {
+    if (h) h->err = f.msg;
+    return f.s;
+  } catch (const std::bad_alloc &) {
+    if (h) h->err = "host allocation failed";
+    return SEM_ENOMEM;
+  } catch (const std::exception &e) {
+    if (h) h->err = e.what();
+    return SEM_EINVAL;
+  }
+}
+thread_local std::string g_setup_err;
+}  // namespace
+
+extern "C" {
+
+sem_status sem_setup(const sem_mesh *mesh, int32_t p, const sem_overlap *overlap,
+                     const sem_weights *weights, const double *nu, int32_t precision,
+                     void *stream, sem_handle *out) {
+  if (!out) return SEM_EINVAL;
+  *out = nullptr;
+  auto *h = new (std::nothrow) sem_ctx();
+  if (!h) return SEM_ENOMEM;
+  h->stream = static_cast<hipStream_t>(stream);
+  if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) {
+    g_setup_err = "unknown precision";
+    delete h;
+    return SEM_EINVAL;
+  }
+  h->precision = precision;
+  sem_status s = guard(h, [&] { setup_impl(h, mesh, p, overlap, weights, nu); });
+  if (s != SEM_OK) {
+    g_setup_err = h->err;
+    delete h;
+    return s;
+  }
+  *out = h;
+  return SEM_OK;
+}
+
+sem_status sem_destroy(sem_handle h) {
+  if (!h) return SEM_EINVAL;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return SEM_OK;
+}
+
+sem_status sem_num_levels(sem_handle h, int32_t *nlevels) {
+  if (!h || !nlevels) return SEM_EINVAL;
+  *nlevels = (int32_t)h->lev.size();
+  return SEM_OK;
+}
+
+sem_status sem_level_info(sem_handle h, int32_t level, int32_t *p_l, int32_t *n_o, int64_t *rows,
+                          int64_t *cols) {
+  if (!h || level < 0 || level >= (int)h->lev.size()) return SEM_EINVAL;
+  const Level &L = h->lev[level];
+  if (p_l) *p_l = L.p;
+  if (n_o) *n_o = L.n_o;
+  if (rows) *rows = L.g.rows;
+  if (cols) *cols = L.g.cols;
+  return SEM_OK;
+}
+
+sem_status sem_node_coords(sem_handle h, int32_t level, double *x, double *y) {
+  if (!h || level < 0 || level >= (int)h->lev.size() || !x || !y) return SEM_EINVAL;
+  const Level &L = h->lev[level];
+  std::copy(L.xc.begin(), L.xc.end(), x);
+  std::copy(L.yc.begin(), L.yc.end(), y);
+  return SEM_OK;
+}
+
+sem_status sem_mass(sem_handle h, const double *f_nodal, double *b) {
+  if (!h || !f_nodal || !b) return SEM_EINVAL;
+  return guard(h, [&] {
+    Level &L = h->lev.back();
+    launch_mass<double>(L.g, f_nodal, b, L.td.w, L.td.mx, L.td.my, h->stream);
+  });
+}
+
+sem_status sem_residual(sem_handle h, int32_t level, const double *u, const double *f, double *r) {
+  if (!h || !u || !r || level < 0 || level >= (int)h->lev.size()) return SEM_EINVAL;
+  return guard(h, [&] { residual<double>(h, level, u, f, r); });
+}
+
+sem_status sem_schwarz_smooth(sem_handle h, int32_t level, double *u, const double *f, int32_t n_it) {
+  if (!h || !u || !f || level < 1 || level >= (int)h->lev.size() || n_it < 0) return SEM_EINVAL;
+  return guard(h, [&] {
+    Level &L = h->lev[level];
+    launch_zero_boundary<double>(L.g, u, h->stream);
+    smooth<double>(h, level, u, f, L.r, n_it, false);
+  });
+}
+
+sem_status sem_restrict(sem_handle h, int32_t level, const double *r_fine, double *f_coarse) {
+  if (!h || !r_fine || !f_coarse || level < 1 || level >= (int)h->lev.size()) return SEM_EINVAL;
+  return guard(h, [&] { restrict_<double>(h, level, r_fine, f_coarse, h->lev[level].t); });
+}
+
+sem_status sem_prolong_add(sem_handle h, int32_t level, const double *u_coarse, double *u_fine) {
+  if (!h || !u_coarse || !u_fine || level < 1 || level >= (int)h->lev.size()) return SEM_EINVAL;
+  return guard(h, [&] { prolong_add<double>(h, level, u_coarse, u_fine, h->lev[level].t); });
+}
+
+sem_status sem_coarse_solve(sem_handle h, const double *f0, double *u0) {
+  if (!h || !f0 || !u0) return SEM_EINVAL;
+  return guard(h, [&] { coarse_solve64(h, f0, u0); });
+}
+
+sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *ns1,
+                      const int32_t *ns2) {
+  if (!h || !u || !f) return SEM_EINVAL;
+  return guard(h, [&] {
+    Level &top = h->lev.back();
+    launch_zero_boundary<double>(top.g, u, h->stream);
+    if (h->precision == SEM_MIXED_FP32) {
+      // MG(u, f) = u + MG(0, f - A u): residual in FP64, cycle in FP32
+      residual<double>(h, (int)h->lev.size() - 1, u, f, h->pr);
+      precondition(h, h->pr, h->pz, ns1, ns2);
+      launch_axpy(1.0, h->pz, u, top.n(), h->stream);
+    } else {
+      vcycle_impl<double>(h, u, f, ns1, ns2, false);
+    }
+  });
+}
+
+sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax, double rtol,
+                         const int32_t *ns1, const int32_t *ns2, int32_t *iters, double *res_hist) {
+  if (!h || !u || !f || imax < 0) return SEM_EINVAL;
+  sem_status conv = SEM_OK;
+  sem_status s = guard(h, [&] {
+    Level &top = h->lev.back();
+    const int L = (int)h->lev.size() - 1;
+    const long n = top.n();
+    hipStream_t st = h->stream;
+    double *r = h->pr, *p = h->pp, *q = h->pq, *z = h->pz, *ro = h->pro;
+    // device scalars: [0] delta, [1] p.q, [2] r.r, [6] z.(r - r_old), [7] z.r, [8] sums
+    double *sc = h->scal;
+    launch_zero_boundary<double>(top.g, u, st);
+    const double *fp = f;
+    if (top.g.periodic) {
+      // project the right side onto the range of A (remove its mean); q is
+      // free until the loop starts
+      HIP_OK(hipMemcpyAsync(q, f, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_sum(q, n, h->partial, sc + 8, st);
+      launch_sub_mean(top.g, q, sc + 8, st);
+      fp = q;
+    }
+    launch_fill<double>(ro, n, 0.0, st);
+    residual<double>(h, L, u, fp, r);
+    launch_dot(r, r, n, h->partial, sc + 2, st);
+    const double r0 = std::sqrt(read_scalar(h, sc + 2));
+    if (!std::isfinite(r0)) throw Fail{SEM_ENAN, "non-finite initial residual"};
+    if (res_hist) res_hist[0] = r0;
+    precondition(h, r, p, ns1, ns2);
+    launch_dot(p, r, n, h->partial, sc + 0, st);
+    int it = 0;
+    bool done = r0 == 0.0;
+    for (it = 1; it <= imax && !done; ++it) {
+      residual<double>(h, L, p, nullptr, q);             // q = A p
+      launch_dot(p, q, n, h->partial, sc + 1, st);       // p.q
+      launch_cg_update(sc, u, p, r, q, n, h->partial, sc + 2, st);  // alpha = delta / p.q
+      const double rn = std::sqrt(read_scalar(h, sc + 2));
+      if (res_hist) res_hist[it] = rn;
+      if (!std::isfinite(rn)) throw Fail{SEM_ENAN, "non-finite residual"};
+      if (rn <= rtol * r0) {
+        done = true;
+        break;
+      }
+      precondition(h, r, z, ns1, ns2);
+      launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
+      launch_cg_direction(sc + 6, sc + 0, p, z, ro, r, n, st);  // beta = z.(r-r_old)/delta
+      launch_copy_scalar(sc + 7, sc + 0, st);            // delta = z.r
+    }
+    if (iters) *iters = done ? std::min(it, imax) : imax;
+    if (!done) conv = SEM_ENOCONV;
+  });
+  if (s != SEM_OK) return s;
+  if (conv != SEM_OK) h->err = "imax reached";
+  return conv;
+}
+
+sem_status sem_norm(sem_handle h, const double *x, double *out) {
+  if (!h || !x || !out) return SEM_EINVAL;
+  return guard(h, [&] {
+    Level &top = h->lev.back();
+    launch_dot(x, x, top.n(), h->partial, h->scal + 10, h->stream);
+    *out = std::sqrt(read_scalar(h, h->scal + 10));
+  });
+}
+
+const char *sem_strerror(sem_status s) {
+  switch (s) {
+    case SEM_OK: return "ok";
+    case SEM_EINVAL: return "invalid argument";
+    case SEM_EDOM: return "argument outside the domain (breaks or nu)";
+    case SEM_ENOMEM: return "out of memory";
+    case SEM_EHIP: return "HIP runtime error";
+    case SEM_ENOCONV: return "no convergence within imax";
+    case SEM_ENAN: return "non-finite value";
+    case SEM_EUNSUP: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+const char *sem_last_error(sem_handle h) { return h ? h->err.c_str() : g_setup_err.c_str(); }
+
+}  // extern "C"

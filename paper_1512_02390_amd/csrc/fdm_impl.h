@@ -1,0 +1,155 @@
+#pragma once
+// Weighted additive Schwarz correction (Section 3.1, Algorithm 2): for every
+// extended element s,
+//     u += R_s^T (W_y (x) W_x) (S_y (x) S_x) D_s (S_y^T (x) S_x^T) R_s r
+// with D_s = diag(1 / (nu_bar_s (lambda_y,i + lambda_x,j))) -- the fast
+// diagonalisation of A_ss^{-1} (Lynch-Rice-Thomas), scaled by 1/nu_bar_s for
+// variable diffusion (Section 4).
+//
+// Mapping onto gfx950: one 64-lane wavefront per work item of EPW = 64/m
+// elements that share their subdomain type in x and in y, so the factor
+// matrices S, S^T are wave-uniform and enter every FMA as a scalar-register
+// operand straight from the scalar cache; no LDS traffic for the operators.
+//   stage 1  lane = tile column j: T1[:, j] = S_y^T r_s[:, j]      (m^2 FMA)
+//   LDS transpose (one m x m tile per element)
+//   stage 2  lane = tile row i:    T2[i, :] = T1[i, :] S_x         (m^2 FMA)
+//            T2 *= D_s
+//   stage 3                        T3[i, :] = T2[i, :] S_x^T       (m^2 FMA)
+//   LDS transpose back
+//   stage 4  lane = tile column j: du[:, j] = W_y S_y T3[:, j]     (m^2 FMA)
+// Each stage loops over its outputs; one output is the dot product of one
+// uniform matrix row (a few wide scalar loads) with the lane's register-
+// resident input vector, so only one matrix row at a time occupies scalar
+// registers, and the result goes straight to LDS (or to the atomic add).
+// The weighted tile is added into u with hardware FP64 atomics (overlapping
+// subdomains touch the same nodes); rounding order therefore varies between
+// runs at the 1e-16 level.
+//
+// Dirichlet boundaries: tile positions that are not unknowns read r = 0 and
+// are never written; their S rows/columns are identity padding with
+// lambda = 1, which keeps them decoupled.
+#include "common.h"
+#include "kernels.h"
+
+namespace sem {
+namespace {
+
+// Dot product of a wave-uniform matrix row (scalar operands) with a
+// register-resident vector, in two interleaved chains.
+template <typename T, int M>
+__device__ __forceinline__ T urow_dot(const T *__restrict__ row, const T (&x)[M]) {
+  T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int i = 0; i + 1 < M; i += 2) {
+    a0 = fma(row[i], x[i], a0);
+    a1 = fma(row[i + 1], x[i + 1], a1);
+  }
+  if constexpr (M % 2) a0 = fma(row[M - 1], x[M - 1], a0);
+  return a0 + a1;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
+  constexpr int EPW = 64 / M;
+  constexpr int LS = M + 1;  // LDS row stride
+  // one tile per element plus a scratch tile for the idle lanes of the wave
+  __shared__ T lds[(EPW + 1) * M * LS];
+  const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
+  const int ty = task->ty, tx = task->tx, cnt = task->count;
+  const int lane = threadIdx.x;
+  const int k = lane / M;
+  const int j = lane - k * M;
+  const bool act = k < cnt;
+  const bool has_tile = k < EPW;
+  const int packed = task->elem[act ? k : 0];
+  const int ey = packed >> 16, ex = packed & 0xffff;
+  const Grid g = A.g;
+  const int per = g.periodic;
+  // wave-uniform factor matrices: every row is read with scalar loads
+  const T *__restrict__ SyT = A.SyT + (long)ty * M * M;   // S_y^T
+  const T *__restrict__ SyW = A.SyW + (long)ty * M * M;   // diag(w_y) S_y
+  const T *__restrict__ Sx = A.Sx + (long)tx * M * M;     // S_x
+  const T *__restrict__ SxT = A.SxT + (long)tx * M * M;   // S_x^T
+  const int row0 = ey * g.p - A.n_o;
+  int gc = ex * g.p - A.n_o + j;
+  bool vc;
+  if (per) {
+    gc = wrap(gc, g.cols);
+    vc = true;
+  } else {
+    vc = gc >= 1 && gc <= g.cols - 2;
+  }
+  T *tile = lds + (has_tile ? k : EPW) * M * LS;
+
+  // ---- gather the residual tile column (branch-free, always in bounds) ----
+  T X[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    int gr = row0 + i;
+    bool ok;
+    if (per) {
+      gr += (gr < 0) ? g.rows : 0;
+      gr -= (gr >= g.rows) ? g.rows : 0;
+      ok = act;
+    } else {
+      ok = act && vc && gr >= 1 && gr <= g.rows - 2;
+    }
+    const long idx = ok ? (long)gr * g.cols + gc : 0;
+    const T v = A.r[idx];
+    X[i] = ok ? v : T(0);
+  }
+  // ---- stage 1: T1 = S_y^T R, lane = column j; row a of T1 -> LDS ----------
+#pragma unroll 1
+  for (int a = 0; a < M; ++a) {
+    tile[a * LS + j] = urow_dot<T, M>(SyT + a * M, X);
+  }
+  __syncthreads();
+  // ---- stage 2: T2 = T1 S_x, lane = row j --------------------------------------
+#pragma unroll
+  for (int b = 0; b < M; ++b) X[b] = tile[j * LS + b];
+  T dv[M];
+  {
+    const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
+    const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
+#pragma unroll
+    for (int c = 0; c < M; ++c) dv[c] = d[c] * s;
+  }
+#pragma unroll 1
+  for (int c = 0; c < M; ++c) {
+    tile[j * LS + c] = urow_dot<T, M>(SxT + c * M, X);
+  }
+  // divide by nu_bar (lambda_y + lambda_x), then stage 3: T3 = T2 S_x^T
+#pragma unroll
+  for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c] * dv[c];
+#pragma unroll 1
+  for (int b = 0; b < M; ++b) {
+    tile[j * LS + b] = urow_dot<T, M>(Sx + b * M, X);
+  }
+  __syncthreads();
+  // ---- stage 4: du = diag(w_y) S_y T3, lane = column j; weighted scatter-add ------
+#pragma unroll
+  for (int a = 0; a < M; ++a) X[a] = tile[a * LS + j];
+  const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
+#pragma unroll 1
+  for (int i = 0; i < M; ++i) {
+    const T v = urow_dot<T, M>(SyW + i * M, X);
+    int gr = row0 + i;
+    bool vr;
+    if (per) {
+      gr = wrap(gr, g.rows);
+      vr = true;
+    } else {
+      vr = gr >= 1 && gr <= g.rows - 2;
+    }
+    if (act && vc && vr) atomic_add(&A.u[(long)gr * g.cols + gc], v * wxj);
+  }
+}
+
+}  // namespace
+
+template <typename T, int M>
+void launch_fdm_m(const FdmArgs<T> &a, hipStream_t s) {
+  if (a.ntasks > 0) hipLaunchKernelGGL((k_fdm<T, M>), dim3(a.ntasks), dim3(64), 0, s, a);
+}
+
+}  // namespace sem

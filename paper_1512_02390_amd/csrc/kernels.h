@@ -1,0 +1,112 @@
+// Device kernels of the SEM Schwarz / p-multigrid solver (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sem {
+
+constexpr int kMaxTile = 48;     // largest subdomain width m = p + 1 + 2 n_o
+constexpr int kMaxOrder = 32;    // largest polynomial order p
+constexpr int kTaskSlots = 24;   // elements per FDM work item (>= 64 / m)
+
+// One FDM work item: up to 64/m elements sharing the same x- and y-type of
+// subdomain (hence the same fast-diagonalisation factors), processed by one
+// 64-wide wavefront with one lane per tile column.
+struct FdmTask {
+  int32_t ty, tx, count, pad;
+  int32_t elem[kTaskSlots];      // (ey << 16) | ex
+};
+
+// Geometry of one level's node array.
+struct Grid {
+  int32_t nx, ny;        // elements
+  int32_t p;             // order
+  int32_t rows, cols;    // node array (Dirichlet includes boundary nodes)
+  int32_t periodic;      // 0 Dirichlet, 1 periodic
+};
+
+template <typename T>
+struct ResidualArgs {
+  Grid g;
+  const T *u, *f;        // f may be null: out = A u
+  T *out;
+  const T *Lhat;         // (p+1)^2 reference stiffness
+  const T *D, *DT;       // (p+1)^2 derivative matrix and its transpose (variable nu)
+  const T *w;            // p+1 GLL weights
+  const T *sx, *sy;      // per element 2/h (x: nx, y: ny)
+  const T *mx, *my;      // per element h/2
+  const T *nu;           // nodal diffusivity (node array) or null
+};
+
+template <typename T>
+struct FdmArgs {
+  Grid g;
+  int32_t n_o, m;
+  const FdmTask *tasks;
+  int32_t ntasks;
+  const T *r;
+  T *u;
+  const T *Sx, *SxT, *SyW, *SyT;  // per type m*m; SyW = diag(w_y) S_y
+  const T *dinv;                  // per (ty, tx) pair m*m
+  int32_t ntx;
+  const T *wx;                    // per x-element m weights
+  const T *nuinv;                 // per element 1/nu_bar or null
+};
+
+template <typename T>
+void launch_residual(const ResidualArgs<T> &a, hipStream_t s);
+template <typename T>
+void launch_fdm(const FdmArgs<T> &a, hipStream_t s);
+
+// 1-D transfer pass along x (dir = 0) or y (dir = 1).  mode 0: prolongation
+// out (+)= E in; mode 1: restriction out = E^T in with each shared fine node
+// counted once.  E is (pf+1) x (pc+1).
+template <typename T>
+void launch_transfer(int dir, int mode, int accumulate, const T *in, int in_rows, int in_cols,
+                     T *out, int out_rows, int out_cols, int n_el, int pf, int pc, int periodic,
+                     const T *E, hipStream_t s);
+
+// C(M x N) = op(A) op(B) on strided views, optional elementwise scale by S
+// (same shape as C, leading dimension lds); C has leading dimension ldc.
+void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const double *B,
+                 long brs, long bcs, double *C, long ldc, const double *S, long lds,
+                 hipStream_t s);
+// y = Minv x on the unknown block of a node array (dense inverse, var nu).
+void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
+                         int nux, double *y, hipStream_t s);
+
+// Vector helpers over whole node arrays of n entries.
+template <typename T>
+void launch_mass(const Grid &g, const T *f, T *b, const T *w, const T *mx, const T *my,
+                 hipStream_t s);
+template <typename T>
+void launch_zero_boundary(const Grid &g, T *x, hipStream_t s);
+template <typename T>
+void launch_fill(T *x, long n, T v, hipStream_t s);
+template <typename Ta, typename Tb>
+void launch_convert(const Ta *in, Tb *out, long n, double scale, hipStream_t s);
+
+// Deterministic two-stage reductions.  partial must hold kRedBlocks doubles
+// per output; results land in device memory res[0..].
+constexpr int kRedBlocks = 512;
+// res[0] = sum x*y
+void launch_dot(const double *x, const double *y, long n, double *partial, double *res,
+                hipStream_t s);
+// res[0] = sum z*(r - ro), res[1] = sum z*r  (Polak-Ribiere numerator, new delta)
+void launch_dot2(const double *z, const double *r, const double *ro, long n, double *partial,
+                 double *res, hipStream_t s);
+// res[0] = sum x
+void launch_sum(const double *x, long n, double *partial, double *res, hipStream_t s);
+// x -= res[0] / count on the unknowns of g (mean removal, periodic)
+void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s);
+// alpha = sc[0] / sc[1]; u += alpha p; r -= alpha q; res = sum r^2
+void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
+                      long n, double *partial, double *res, hipStream_t s);
+// beta = num[0] / den[0]; p = z + beta p; ro = r
+void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
+                         double *ro, const double *r, long n, hipStream_t s);
+// y += alpha x
+void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s);
+void launch_copy_scalar(const double *src, double *dst, hipStream_t s);
+
+}  // namespace sem

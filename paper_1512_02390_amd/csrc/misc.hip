@@ -1,0 +1,374 @@
+// Transfers between p-levels (Section 3.2), the coarse-grid solve and the
+// vector kernels of the multigrid-preconditioned CG (Section 3.3).
+#include "common.h"
+#include "kernels.h"
+
+namespace sem {
+namespace {
+
+// ---------------------------------------------------------------------------
+// 1-D transfer along one direction, one thread per output node.
+//   prolongation (mode 0): out[I] = sum_c E[a][c] in[e pc + c], with e, a the
+//     element and local index of fine node I;
+//   restriction  (mode 1): out[J] = sum_a E[a][g] in[e pf + a] (+ the left
+//     element's interior nodes when J is an element boundary node), i.e. the
+//     transpose of the assembled prolongation, each fine node counted once.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_transfer(int dir, int mode, int acc, int zero_bnd, const T *__restrict__ in,
+                           int in_rows, int in_cols, T *__restrict__ out, int out_rows,
+                           int out_cols, int n_el, int pf, int pc, int periodic,
+                           const T *__restrict__ E) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)out_rows * out_cols) return;
+  const int orow = (int)(idx / out_cols), ocol = (int)(idx - (long)orow * out_cols);
+  if (zero_bnd && !periodic &&
+      (orow == 0 || ocol == 0 || orow == out_rows - 1 || ocol == out_cols - 1)) {
+    if (!acc) out[idx] = T(0);
+    return;
+  }
+  const int I = dir == 0 ? ocol : orow;
+  const int other = dir == 0 ? orow : ocol;
+  const int nin = dir == 0 ? in_cols : in_rows;
+  auto IN = [&](int k) -> T {
+    if (periodic) k = wrap(k, nin);
+    return dir == 0 ? in[(long)other * in_cols + k] : in[(long)k * in_cols + other];
+  };
+  T v = T(0);
+  const int ldE = pc + 1;
+  if (mode == 0) {
+    const int e = min(I / pf, n_el - 1);
+    const int a = I - e * pf;
+    for (int c = 0; c <= pc; ++c) v = fma(E[a * ldE + c], IN(e * pc + c), v);
+  } else {
+    const int e = min(I / pc, n_el - 1);
+    const int gl = I - e * pc;
+    for (int a = 0; a <= pf; ++a) v = fma(E[a * ldE + gl], IN(e * pf + a), v);
+    if (gl == 0 && (periodic || e > 0)) {
+      const int em = periodic ? wrap(e - 1, n_el) : e - 1;
+      for (int a = 0; a < pf; ++a) v = fma(E[a * ldE + pc], IN(em * pf + a), v);
+    }
+  }
+  out[idx] = acc ? out[idx] + v : v;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense GEMM (coarse fast diagonalisation), 16x16 tiles.
+// ---------------------------------------------------------------------------
+constexpr int TB = 16;
+__global__ void k_gemm(int M, int N, int K, const double *__restrict__ A, long ars, long acs,
+                       const double *__restrict__ B, long brs, long bcs, double *__restrict__ C,
+                       long ldc, const double *__restrict__ S, long lds_) {
+  __shared__ double sa[TB][TB + 1], sb[TB][TB + 1];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int row = blockIdx.y * TB + ty, col = blockIdx.x * TB + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < K; k0 += TB) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    sa[ty][tx] = (row < M && ka < K) ? A[row * ars + ka * acs] : 0.0;
+    sb[ty][tx] = (kb < K && col < N) ? B[kb * brs + col * bcs] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TB; ++k) acc = fma(sa[ty][k], sb[k][tx], acc);
+    __syncthreads();
+  }
+  if (row < M && col < N) {
+    if (S) acc *= S[row * lds_ + col];
+    C[row * ldc + col] = acc;
+  }
+}
+
+// y[unknown i] = sum_j Minv[i][j] x[unknown j]; unknowns form an nux-wide
+// block starting at xoff of a node array with xcols columns.
+__global__ void k_dense_matvec(int n, const double *__restrict__ Minv,
+                               const double *__restrict__ x, long xoff, int xcols, int nux,
+                               double *__restrict__ y) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int jr = j / nux, jc = j - jr * nux;
+    s = fma(Minv[(long)i * n + j], x[xoff + (long)jr * xcols + jc], s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int ir = i / nux, ic = i - ir * nux;
+    y[xoff + (long)ir * xcols + ic] = red[0];
+  }
+}
+
+// b = M f at unknowns, 0 at Dirichlet boundary nodes.
+template <typename T>
+__global__ void k_mass(Grid g, const T *__restrict__ f, T *__restrict__ b, const T *__restrict__ w,
+                       const T *__restrict__ mx, const T *__restrict__ my) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)g.rows * g.cols) return;
+  const int row = (int)(idx / g.cols), col = (int)(idx - (long)row * g.cols);
+  if (!g.periodic && (row == 0 || col == 0 || row == g.rows - 1 || col == g.cols - 1)) {
+    b[idx] = T(0);
+    return;
+  }
+  auto diag = [&](int i, int n_el, const T *h) -> T {
+    int e = min(i / g.p, n_el - 1);
+    int a = i - e * g.p;
+    T v = h[e] * w[a];
+    if (a == 0 && (g.periodic || e > 0)) v += h[g.periodic ? wrap(e - 1, n_el) : e - 1] * w[g.p];
+    return v;
+  };
+  b[idx] = diag(row, g.ny, my) * diag(col, g.nx, mx) * f[idx];
+}
+
+template <typename T>
+__global__ void k_zero_boundary(Grid g, T *__restrict__ x) {
+  const long n = 2L * g.cols + 2L * g.rows;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  long pos;
+  if (idx < g.cols)
+    pos = idx;
+  else if (idx < 2L * g.cols)
+    pos = (long)(g.rows - 1) * g.cols + (idx - g.cols);
+  else if (idx < 2L * g.cols + g.rows)
+    pos = (idx - 2L * g.cols) * g.cols;
+  else
+    pos = (idx - 2L * g.cols - g.rows) * g.cols + g.cols - 1;
+  x[pos] = T(0);
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ x, long n, T v) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) x[idx] = v;
+}
+
+template <typename Ta, typename Tb>
+__global__ void k_convert(const Ta *__restrict__ in, Tb *__restrict__ out, long n, double scale) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) out[idx] = (Tb)((double)in[idx] * scale);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions: kRedBlocks partial sums per output, then one
+// block adds them in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int RT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = RT / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y, long n,
+                              double *__restrict__ partial) {
+  __shared__ double red[RT];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT)
+    s = fma(x[i], y[i], s);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_dot2_partial(const double *__restrict__ z, const double *__restrict__ r,
+                               const double *__restrict__ ro, long n, double *__restrict__ partial) {
+  __shared__ double red[RT];
+  double s0 = 0.0, s1 = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+    s0 = fma(z[i], r[i] - ro[i], s0);
+    s1 = fma(z[i], r[i], s1);
+  }
+  s0 = block_sum(s0, red);
+  __syncthreads();
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[kRedBlocks + blockIdx.x] = s1;
+  }
+}
+
+__global__ void k_sum_partial(const double *__restrict__ x, long n, double *__restrict__ partial) {
+  __shared__ double red[RT];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) s += x[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// res[k] = sum of partial[k * kRedBlocks ...]; one block per output
+__global__ void k_reduce_final(const double *__restrict__ partial, int nb, double *__restrict__ res) {
+  __shared__ double red[RT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RT) s += partial[blockIdx.x * kRedBlocks + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) res[blockIdx.x] = s;
+}
+
+__global__ void k_sub_mean(Grid g, double *__restrict__ x, const double *__restrict__ sum) {
+  const long n = (long)g.rows * g.cols;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) x[idx] -= sum[0] / (double)n;
+}
+
+__global__ void k_cg_update(const double *__restrict__ sc, double *__restrict__ u,
+                            const double *__restrict__ p, double *__restrict__ r,
+                            const double *__restrict__ q, long n, double *__restrict__ partial) {
+  __shared__ double red[RT];
+  const double alpha = sc[0] / sc[1];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+    u[i] = fma(alpha, p[i], u[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    s = fma(ri, ri, s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_cg_direction(const double *__restrict__ num, const double *__restrict__ den,
+                               double *__restrict__ p, const double *__restrict__ z,
+                               double *__restrict__ ro, const double *__restrict__ r, long n) {
+  const double beta = num[0] / den[0];
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) {
+    p[idx] = fma(beta, p[idx], z[idx]);
+    ro[idx] = r[idx];
+  }
+}
+
+__global__ void k_axpy(double alpha, const double *__restrict__ x, double *__restrict__ y, long n) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) y[idx] = fma(alpha, x[idx], y[idx]);
+}
+
+__global__ void k_copy_scalar(const double *__restrict__ src, double *__restrict__ dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+int red_blocks(long n) {
+  long b = (n + RT - 1) / RT;
+  return (int)(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_transfer(int dir, int mode, int accumulate, const T *in, int in_rows, int in_cols,
+                     T *out, int out_rows, int out_cols, int n_el, int pf, int pc, int periodic,
+                     const T *E, hipStream_t s) {
+  const long n = (long)out_rows * out_cols;
+  // the last pass of a transfer writes the final level array: keep its
+  // Dirichlet boundary at zero
+  const int zero_bnd = (dir == 1);
+  hipLaunchKernelGGL(k_transfer<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, dir, mode,
+                     accumulate, zero_bnd, in, in_rows, in_cols, out, out_rows, out_cols, n_el, pf,
+                     pc, periodic, E);
+}
+template void launch_transfer<double>(int, int, int, const double *, int, int, double *, int, int,
+                                      int, int, int, int, const double *, hipStream_t);
+template void launch_transfer<float>(int, int, int, const float *, int, int, float *, int, int,
+                                     int, int, int, int, const float *, hipStream_t);
+
+void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const double *B,
+                 long brs, long bcs, double *C, long ldc, const double *S, long lds,
+                 hipStream_t s) {
+  dim3 grid(ceil_div(N, TB), ceil_div(M, TB));
+  hipLaunchKernelGGL(k_gemm, grid, dim3(TB, TB), 0, s, M, N, K, A, ars, acs, B, brs, bcs, C, ldc,
+                     S, lds);
+}
+
+void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
+                         int nux, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_matvec, dim3(n), dim3(256), 0, s, n, Minv, x, xoff, xcols, nux, y);
+}
+
+template <typename T>
+void launch_mass(const Grid &g, const T *f, T *b, const T *w, const T *mx, const T *my,
+                 hipStream_t s) {
+  const long n = (long)g.rows * g.cols;
+  hipLaunchKernelGGL(k_mass<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, g, f, b, w, mx, my);
+}
+template void launch_mass<double>(const Grid &, const double *, double *, const double *,
+                                  const double *, const double *, hipStream_t);
+
+template <typename T>
+void launch_zero_boundary(const Grid &g, T *x, hipStream_t s) {
+  if (g.periodic) return;
+  const long n = 2L * g.cols + 2L * g.rows;
+  hipLaunchKernelGGL(k_zero_boundary<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, g, x);
+}
+template void launch_zero_boundary<double>(const Grid &, double *, hipStream_t);
+template void launch_zero_boundary<float>(const Grid &, float *, hipStream_t);
+
+template <typename T>
+void launch_fill(T *x, long n, T v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, x, n, v);
+}
+template void launch_fill<double>(double *, long, double, hipStream_t);
+template void launch_fill<float>(float *, long, float, hipStream_t);
+
+template <typename Ta, typename Tb>
+void launch_convert(const Ta *in, Tb *out, long n, double scale, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL((k_convert<Ta, Tb>), dim3(ceil_div(n, 256)), dim3(256), 0, s, in, out, n,
+                       scale);
+}
+template void launch_convert<double, float>(const double *, float *, long, double, hipStream_t);
+template void launch_convert<float, double>(const float *, double *, long, double, hipStream_t);
+
+void launch_dot(const double *x, const double *y, long n, double *partial, double *res,
+                hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(RT), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+}
+
+void launch_dot2(const double *z, const double *r, const double *ro, long n, double *partial,
+                 double *res, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_dot2_partial, dim3(nb), dim3(RT), 0, s, z, r, ro, n, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(2), dim3(RT), 0, s, partial, nb, res);
+}
+
+void launch_sum(const double *x, long n, double *partial, double *res, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(RT), 0, s, x, n, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+}
+
+void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s) {
+  const long n = (long)g.rows * g.cols;
+  hipLaunchKernelGGL(k_sub_mean, dim3(ceil_div(n, 256)), dim3(256), 0, s, g, x, sum);
+}
+
+void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
+                      long n, double *partial, double *res, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RT), 0, s, sc, u, p, r, q, n, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+}
+
+void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
+                         double *ro, const double *r, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(ceil_div(n, 256)), dim3(256), 0, s, num, den, p, z, ro,
+                     r, n);
+}
+
+void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, s, alpha, x, y, n);
+}
+
+void launch_copy_scalar(const double *src, double *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, s, src, dst);
+}
+
+}  // namespace sem

@@ -1,0 +1,224 @@
+"""Python binding of libsem (include/sem.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; this module converts torch
+device tensors to pointers and host numpy arrays to C arrays.  If the shared
+library is missing, importing works but creating a Solver raises, so that no
+code path silently falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsem.so")
+
+BC_DIRICHLET, BC_PERIODIC = 0, 1
+W_TOPHAT, W_ARITH = -1, -2
+NO_FIXED, NO_CEIL_P8, NO_FLOOR_P8, NO_CEIL_P2 = 0, 1, 2, 3
+FP64, MIXED_FP32 = 0, 1
+
+STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EDOM", -3: "SEM_ENOMEM", -4: "SEM_EHIP",
+          -5: "SEM_ENOCONV", -6: "SEM_ENAN", -7: "SEM_EUNSUP"}
+
+EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_node_coords",
+           "sem_mass", "sem_residual", "sem_schwarz_smooth", "sem_restrict", "sem_prolong_add",
+           "sem_coarse_solve", "sem_vcycle", "sem_pcg_solve", "sem_norm", "sem_strerror",
+           "sem_last_error"]
+
+
+class SemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("xb", C.POINTER(C.c_double)),
+                ("yb", C.POINTER(C.c_double)), ("bc", C.c_int32)]
+
+
+class _Overlap(C.Structure):
+    _fields_ = [("rule", C.c_int32), ("n_o", C.c_int32)]
+
+
+class _Weights(C.Structure):
+    _fields_ = [("wf", C.c_int32), ("alpha_x", C.POINTER(C.c_double)),
+                ("alpha_y", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsem.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with python -m paper_1512_02390_amd.build")
+    lib = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.sem_setup.argtypes = [C.POINTER(_Mesh), I32, C.POINTER(_Overlap), C.POINTER(_Weights),
+                              C.POINTER(D), I32, P, C.POINTER(P)]
+    lib.sem_destroy.argtypes = [P]
+    lib.sem_num_levels.argtypes = [P, C.POINTER(I32)]
+    lib.sem_level_info.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I64),
+                                   C.POINTER(I64)]
+    lib.sem_node_coords.argtypes = [P, I32, C.POINTER(D), C.POINTER(D)]
+    lib.sem_mass.argtypes = [P, P, P]
+    lib.sem_residual.argtypes = [P, I32, P, P, P]
+    lib.sem_schwarz_smooth.argtypes = [P, I32, P, P, I32]
+    lib.sem_restrict.argtypes = [P, I32, P, P]
+    lib.sem_prolong_add.argtypes = [P, I32, P, P]
+    lib.sem_coarse_solve.argtypes = [P, P, P]
+    lib.sem_vcycle.argtypes = [P, P, P, C.POINTER(I32), C.POINTER(I32)]
+    lib.sem_pcg_solve.argtypes = [P, P, P, I32, D, C.POINTER(I32), C.POINTER(I32),
+                                  C.POINTER(I32), C.POINTER(D)]
+    lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
+    lib.sem_strerror.argtypes = [I32]
+    lib.sem_strerror.restype = C.c_char_p
+    lib.sem_last_error.argtypes = [P]
+    lib.sem_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("sem_strerror", "sem_last_error"):
+            getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _i32_array(v):
+    if v is None:
+        return None
+    a = (C.c_int32 * len(v))(*[int(x) for x in v])
+    return a
+
+
+class Solver:
+    """Handle of one SEM problem (all multigrid levels) on the current device."""
+
+    def __init__(self, xb, yb, p: int, bc: int = BC_DIRICHLET, overlap_rule: int = NO_FIXED,
+                 n_o: int = 1, wf: int = 5, nu=None, precision: int = FP64, alpha_x=None,
+                 alpha_y=None, stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self._xb = np.ascontiguousarray(xb, dtype=np.float64)
+        self._yb = np.ascontiguousarray(yb, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        mesh = _Mesh(len(self._xb) - 1, len(self._yb) - 1, self._xb.ctypes.data_as(dp),
+                     self._yb.ctypes.data_as(dp), bc)
+        ov = _Overlap(overlap_rule, n_o)
+        self._ax = None if alpha_x is None else np.ascontiguousarray(alpha_x, dtype=np.float64)
+        self._ay = None if alpha_y is None else np.ascontiguousarray(alpha_y, dtype=np.float64)
+        wts = _Weights(wf, None if self._ax is None else self._ax.ctypes.data_as(dp),
+                       None if self._ay is None else self._ay.ctypes.data_as(dp))
+        nu_host = None
+        if nu is not None:
+            nu_host = np.ascontiguousarray(nu, dtype=np.float64)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.sem_setup(C.byref(mesh), p, C.byref(ov), C.byref(wts),
+                                None if nu_host is None else nu_host.ctypes.data_as(dp),
+                                precision, C.c_void_p(stream), C.byref(h))
+        if st != 0:
+            raise SemError(st, self.lib.sem_last_error(None).decode())
+        self.h = h
+        self.p = p
+        self.bc = bc
+        n = C.c_int32()
+        self.lib.sem_num_levels(self.h, C.byref(n))
+        self.nlevels = n.value
+        self.L = self.nlevels - 1
+
+    def _check(self, st):
+        if st != 0:
+            raise SemError(st, self.lib.sem_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout ---------------------------------------------------------------
+    def level_info(self, level: int):
+        pl, no = C.c_int32(), C.c_int32()
+        r, c = C.c_int64(), C.c_int64()
+        self._check(self.lib.sem_level_info(self.h, level, C.byref(pl), C.byref(no), C.byref(r),
+                                            C.byref(c)))
+        return pl.value, no.value, r.value, c.value
+
+    def shape(self, level: int | None = None):
+        _, _, r, c = self.level_info(self.L if level is None else level)
+        return r, c
+
+    def node_coords(self, level: int | None = None):
+        level = self.L if level is None else level
+        r, c = self.shape(level)
+        x = np.zeros(c)
+        y = np.zeros(r)
+        dp = C.POINTER(C.c_double)
+        self._check(self.lib.sem_node_coords(self.h, level, x.ctypes.data_as(dp),
+                                             y.ctypes.data_as(dp)))
+        return x, y
+
+    def zeros(self, level: int | None = None):
+        return self.torch.zeros(self.shape(level), dtype=self.torch.float64, device="cuda")
+
+    # -- operations -------------------------------------------------------------
+    def mass(self, f_nodal, b):
+        self._check(self.lib.sem_mass(self.h, _ptr(f_nodal), _ptr(b)))
+
+    def residual(self, level: int, u, f, r):
+        self._check(self.lib.sem_residual(self.h, level, _ptr(u), _ptr(f), _ptr(r)))
+
+    def schwarz_smooth(self, level: int, u, f, n_it: int = 1):
+        self._check(self.lib.sem_schwarz_smooth(self.h, level, _ptr(u), _ptr(f), n_it))
+
+    def restrict(self, level: int, r_fine, f_coarse):
+        self._check(self.lib.sem_restrict(self.h, level, _ptr(r_fine), _ptr(f_coarse)))
+
+    def prolong_add(self, level: int, u_coarse, u_fine):
+        self._check(self.lib.sem_prolong_add(self.h, level, _ptr(u_coarse), _ptr(u_fine)))
+
+    def coarse_solve(self, f0, u0):
+        self._check(self.lib.sem_coarse_solve(self.h, _ptr(f0), _ptr(u0)))
+
+    def vcycle(self, u, f, ns1=None, ns2=None):
+        self._check(self.lib.sem_vcycle(self.h, _ptr(u), _ptr(f), _i32_array(ns1),
+                                        _i32_array(ns2)))
+
+    def pcg_solve(self, u, f, imax: int = 100, rtol: float = 1e-10, ns1=None, ns2=None):
+        """Returns (iterations, residual history, converged)."""
+        it = C.c_int32()
+        hist = np.zeros(imax + 1)
+        st = self.lib.sem_pcg_solve(self.h, _ptr(u), _ptr(f), imax, rtol, _i32_array(ns1),
+                                    _i32_array(ns2), C.byref(it),
+                                    hist.ctypes.data_as(C.POINTER(C.c_double)))
+        if st not in (0, -5):
+            self._check(st)
+        return it.value, hist[: it.value + 1], st == 0
+
+    def norm(self, x) -> float:
+        out = C.c_double()
+        self._check(self.lib.sem_norm(self.h, _ptr(x), C.byref(out)))
+        return out.value

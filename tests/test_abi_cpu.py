@@ -1,0 +1,63 @@
+"""Host-only checks of the C-ABI boundary: the shared library loads, exports
+every function declared in include/sem.h, the header is valid C, and error
+handling that needs no device works."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sem.h")
+LIB = os.path.join(ROOT, "paper_1512_02390_amd", "libsem.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sem_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_is_c():
+    src = f'#include "{HEADER}"\nint main(void) {{ return 0; }}\n'
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-x", "c", "-fsyntax-only", "-"],
+                       input=src, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert "sem_setup" in names and "sem_pcg_solve" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1512_02390_amd import sem
+    assert sorted(sem.EXPORTS) == names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_error_paths_without_device():
+    lib = ctypes.CDLL(LIB)
+    lib.sem_strerror.restype = ctypes.c_char_p
+    lib.sem_strerror.argtypes = [ctypes.c_int32]
+    assert lib.sem_strerror(-5) == b"no convergence within imax"
+    # null handle / null output are rejected before any device call
+    lib.sem_setup.restype = ctypes.c_int32
+    assert lib.sem_setup(None, 4, None, None, None, 0, None, None) == -1
+    lib.sem_destroy.restype = ctypes.c_int32
+    assert lib.sem_destroy(None) == -1
+    lib.sem_norm.restype = ctypes.c_int32
+    assert lib.sem_norm(None, None, None) == -1
+
+
+def test_solver_refuses_missing_library(tmp_path):
+    from paper_1512_02390_amd import sem
+    saved = sem._lib
+    sem._lib = None
+    try:
+        with pytest.raises(OSError):
+            sem.load_library(str(tmp_path / "missing.so"))
+    finally:
+        sem._lib = saved
