@@ -18,6 +18,7 @@ from __future__ import annotations
 from dataclasses import dataclass
 
 import numpy as np
+import scipy.sparse as sps
 
 from .gll import gll, derivative_matrix, element_matrices
 
@@ -84,6 +85,9 @@ class Space:
         self.ay = Axis(yb, p, bc)
         self.Lx, self.Mx = self.ax.assemble()
         self.Ly, self.My = self.ay.assemble()
+        # the same matrices in sparse storage, used to apply the operator
+        self._sLx, self._sMx = sps.csr_matrix(self.Lx), sps.csr_matrix(self.Mx)
+        self._sLy, self._sMy = sps.csr_matrix(self.Ly), sps.csr_matrix(self.My)
         self.shape = (self.ay.N, self.ax.N)
         self.mask = self.ay.unknown_mask()[:, None] & self.ax.unknown_mask()[None, :]
 
@@ -101,7 +105,10 @@ class Space:
     def apply_A(self, U):
         """A u = (M_y (x) L_x + L_y (x) M_x) u on the unknowns."""
         U = self.zero_boundary(U)
-        return self.zero_boundary(self.My @ U @ self.Lx.T + self.Ly @ U @ self.Mx.T)
+        # M_y U L_x^T + L_y U M_x^T, each product taken with the sparse factor
+        t1 = self._sMy @ (self._sLx @ U.T).T
+        t2 = self._sLy @ (self._sMx @ U.T).T
+        return self.zero_boundary(t1 + t2)
 
     def mass(self, F):
         """(M_y (x) M_x) f for nodal values f: the discrete right-hand side."""

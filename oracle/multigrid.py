@@ -22,6 +22,9 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sps
+import scipy.sparse.linalg as spla
 
 from .discretization import PERIODIC, Space, element_mean
 from .gll import gll, lagrange_matrix
@@ -83,8 +86,8 @@ class Multigrid:
         self.spaces = [Space(xb, yb, q, bc) for q in self.orders]
         self.overlaps = [0] + [level_overlap(overlap_rule, n_o, q) for q in self.orders[1:]]
         self.P = [None] + [
-            (prolongation_1d(self.spaces[l - 1].ax, self.spaces[l].ax),
-             prolongation_1d(self.spaces[l - 1].ay, self.spaces[l].ay))
+            (sps.csr_matrix(prolongation_1d(self.spaces[l - 1].ax, self.spaces[l].ax)),
+             sps.csr_matrix(prolongation_1d(self.spaces[l - 1].ay, self.spaces[l].ay)))
             for l in range(1, self.L + 1)]
         # variable diffusion: nu per level and element means from the top level
         self.NU = None
@@ -109,12 +112,12 @@ class Multigrid:
     def prolong(self, l: int, Uc):
         """I_l u_{l-1} = P_y U_c P_x^T."""
         Px, Py = self.P[l]
-        return self.spaces[l].zero_boundary(Py @ Uc @ Px.T)
+        return self.spaces[l].zero_boundary(Py @ (Px @ Uc.T).T)
 
     def restrict(self, l: int, R):
         """I_l^T r = P_y^T R P_x."""
         Px, Py = self.P[l]
-        return self.spaces[l - 1].zero_boundary(Py.T @ R @ Px)
+        return self.spaces[l - 1].zero_boundary(Py.T @ (Px.T @ R.T).T)
 
     def smooth(self, l: int, U, F, n_it: int):
         if n_it == 0:
@@ -124,12 +127,25 @@ class Multigrid:
 
     # -- coarse grid ------------------------------------------------------------
     def _coarse_setup(self):
+        """Factor A_0 once.  Dirichlet Poisson: sparse LU of the Kronecker form
+        (size grows with the mesh); otherwise dense Cholesky of A_0 (+ c 1 1^T
+        when periodic, which is SPD and leaves A_0^+ f unchanged on the range)."""
         s = self.spaces[0]
+        self.A0_lu = None
+        if self.NU is None and self.bc != PERIODIC:
+            mx, my = s.ax.unknown_mask(), s.ay.unknown_mask()
+            Lx = sps.csr_matrix(s.Lx[np.ix_(mx, mx)])
+            Mx = sps.csr_matrix(s.Mx[np.ix_(mx, mx)])
+            Ly = sps.csr_matrix(s.Ly[np.ix_(my, my)])
+            My = sps.csr_matrix(s.My[np.ix_(my, my)])
+            A0 = (sps.kron(My, Lx) + sps.kron(Ly, Mx)).tocsc()
+            self.A0_lu = spla.splu(A0)
+            return
         A0 = s.dense_A() if self.NU is None else s.dense_B(self.NU[0])
         if self.bc == PERIODIC:
             n = A0.shape[0]
             A0 = A0 + (np.trace(A0) / n ** 2) * np.ones((n, n))
-        self.A0 = A0
+        self.A0_factor = sla.cho_factor(A0)
 
     def coarse_solve(self, F0):
         """u_0 = A_0^+ f_0 (Algorithm 3, coarse grid solution)."""
@@ -137,7 +153,10 @@ class Multigrid:
         f = F0[s.mask]
         if self.bc == PERIODIC:
             f = f - f.mean()
-        u = np.linalg.solve(self.A0, f)
+        if self.A0_lu is not None:
+            u = self.A0_lu.solve(f)
+        else:
+            u = sla.cho_solve(self.A0_factor, f)
         if self.bc == PERIODIC:
             u = u - u.mean()
         U = np.zeros(s.shape)

@@ -34,6 +34,7 @@ def test_prolongation_reproduces_coarse_polynomials():
     for l in range(1, mg.L + 1):
         pc = mg.orders[l - 1]
         Px, Py = mg.P[l]
+        Px, Py = Px.toarray(), Py.toarray()
         xc, xf = mg.spaces[l - 1].ax.coords(), mg.spaces[l].ax.coords()
         yc, yf = mg.spaces[l - 1].ay.coords(), mg.spaces[l].ay.coords()
         for k in range(pc + 1):
@@ -49,7 +50,7 @@ def test_prolongation_periodic_elementwise():
     xb = W.uniform_breaks(4, 1.0)
     mg = Multigrid(xb, xb, 8, PERIODIC)
     for l in range(1, mg.L + 1):
-        Px, _ = mg.P[l]
+        Px = mg.P[l][0].toarray()
         ac, af = mg.spaces[l - 1].ax, mg.spaces[l].ax
         # hat-like continuous periodic function: 1 - xi^2 per element (degree 2)
         if ac.p < 2:
