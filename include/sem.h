@@ -8,7 +8,7 @@
  * Conventions shared by every entry point
  *  - Vectors are nodal arrays of one multigrid level, FP64, row-major with
  *    rows along y and columns along x, `rows * cols` contiguous doubles in
- *    device memory (sizes from sem_layout).  Dirichlet arrays include the
+ *    device memory (sizes from sem_level_info).  Dirichlet arrays include the
  *    boundary nodes; their entries are ignored on input and written as 0.
  *    Periodic arrays hold n*p nodes per direction (node n*p is node 0).
  *  - The caller owns every vector passed in; the handle owns all tables and
@@ -146,6 +146,16 @@ sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *n
 sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax, double rtol,
                          const int32_t *ns1, const int32_t *ns2, int32_t *iters,
                          double *res_hist);
+
+/* Kernel timing for measurement: when enabled for `level`, every launch of
+ * the fast-diagonalisation Schwarz kernel on that level (the dominant kernel
+ * of the cycle) is bracketed by a pair of HIP events on the handle's stream.
+ * sem_timing_read synchronises the stream and returns the number of timed
+ * launches and their summed duration in milliseconds, then clears the
+ * record.  At most 65536 launches are recorded between reads; later launches
+ * are not timed.  on = 0 disables recording. */
+sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on);
+sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms);
 
 /* Euclidean norm of the unknowns of a level-L array (synchronises). */
 sem_status sem_norm(sem_handle h, const double *x, double *out);

@@ -124,7 +124,14 @@ struct sem_ctx {
   // PCG / reductions
   double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr, *pro = nullptr;
   double *partial = nullptr, *scal = nullptr;  // scal: device scalars
+  // optional event timing of the Schwarz kernel on one level
+  int time_level = -1;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
   std::string err;
+  ~sem_ctx() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -659,7 +666,13 @@ void fdm(sem_ctx *h, int l, const T *r, T *u) {
   Tables<T> &t = tabs<T>(L);
   FdmArgs<T> a{L.g, L.n_o, L.m, L.tasks, L.ntasks, r, u, t.Sx, t.SxT, t.SyW, t.SyT, t.dinv, L.ntx,
                t.wx, t.nuinv};
+  const bool timed = (l == h->time_level) && h->ev_used + 2 <= h->ev.size();
+  if (timed) HIP_OK(hipEventRecord(h->ev[h->ev_used], h->stream));
   launch_fdm<T>(a, h->stream);
+  if (timed) {
+    HIP_OK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
+    h->ev_used += 2;
+  }
 }
 
 // n_it sweeps of Algorithm 2; if u_is_zero the first residual is f itself.
@@ -1005,6 +1018,38 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
   if (s != SEM_OK) return s;
   if (conv != SEM_OK) h->err = "imax reached";
   return conv;
+}
+
+sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on) {
+  if (!h || level < 1 || level >= (int)h->lev.size()) return SEM_EINVAL;
+  return guard(h, [&] {
+    if (on) {
+      if (h->ev.empty()) {
+        h->ev.resize(2 * 65536);
+        for (auto &e : h->ev) HIP_OK(hipEventCreate(&e));
+      }
+      h->time_level = level;
+    } else {
+      h->time_level = -1;
+    }
+    h->ev_used = 0;
+  });
+}
+
+sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms) {
+  if (!h || !count || !total_ms) return SEM_EINVAL;
+  return guard(h, [&] {
+    HIP_OK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+      tot += ms;
+    }
+    *count = (int64_t)(h->ev_used / 2);
+    *total_ms = tot;
+    h->ev_used = 0;
+  });
 }
 
 sem_status sem_norm(sem_handle h, const double *x, double *out) {

@@ -26,7 +26,7 @@ STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EDOM", -3: "SEM_ENOMEM", -4: "
 EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_node_coords",
            "sem_mass", "sem_residual", "sem_schwarz_smooth", "sem_restrict", "sem_prolong_add",
            "sem_coarse_solve", "sem_vcycle", "sem_pcg_solve", "sem_norm", "sem_strerror",
-           "sem_last_error"]
+           "sem_last_error", "sem_timing_enable", "sem_timing_read"]
 
 
 class SemError(RuntimeError):
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.sem_pcg_solve.argtypes = [P, P, P, I32, D, C.POINTER(I32), C.POINTER(I32),
                                   C.POINTER(I32), C.POINTER(D)]
     lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
+    lib.sem_timing_enable.argtypes = [P, I32, I32]
+    lib.sem_timing_read.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
     lib.sem_strerror.argtypes = [I32]
     lib.sem_strerror.restype = C.c_char_p
     lib.sem_last_error.argtypes = [P]
@@ -217,6 +219,15 @@ class Solver:
         if st not in (0, -5):
             self._check(st)
         return it.value, hist[: it.value + 1], st == 0
+
+    def timing_enable(self, level: int, on: bool = True):
+        self._check(self.lib.sem_timing_enable(self.h, level, 1 if on else 0))
+
+    def timing_read(self):
+        """(number of timed Schwarz-kernel launches, summed milliseconds)."""
+        n, ms = C.c_int64(), C.c_double()
+        self._check(self.lib.sem_timing_read(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     def norm(self, x) -> float:
         out = C.c_double()
