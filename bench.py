@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the SEM Schwarz / p-multigrid solver on one MI355X.
+
+A step is one complete solve of the workload with the multigrid-preconditioned
+CG (MGCG(1,0): one pre-smoothing per level) from the seeded initial guess to
+a residual reduction of 1e-10: it runs every part of the hot path (residual,
+Schwarz smoother, restriction, prolongation, coarse solve, V-cycle, CG).
+
+Printed JSON line (one):
+  value        DOF/s per V-cycle over the timed solves: finest-level unknowns
+               times V-cycles executed, divided by the wall time of the solves
+  ms_per_step  time to 1e-10 per solve
+  roofline     the finest-level Schwarz kernel, timed with HIP events on the
+               library's stream during the timed solves
+  cpu_baseline the CPU oracle on a bounded sample of the same workload
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload c2] [--n-o 1]
+                       [--precision fp64|mixed] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFS = 78.6         # MI355X FP64 vector
+FP32_PEAK_TFS = 157.3        # MI355X FP32 vector
+RIDGE_FP64 = FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+RIDGE_FP32 = FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fdm_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fdm_impl.h", "kernels.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1512_02390_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_problem(name: str, n_o: int, precision: int):
+    import numpy as np
+    import torch
+    from paper_1512_02390_amd import workloads as W
+    from paper_1512_02390_amd.sem import Solver
+
+    cfg = W.config(name, n_o)
+    nu = None
+    NU = None
+    if cfg.variable_nu:
+        nu = W.GaussianFieldNu()
+    if nu is not None:
+        # node coordinates from a constant-coefficient handle of the same mesh
+        probe = Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5)
+        xc, yc = probe.node_coords()
+        probe.close()
+        NU = W.nodal(nu.nu, xc, yc)
+    s = Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
+               precision=precision)
+    shape = s.shape()
+    if name == "c1":
+        xc, yc = s.node_coords()
+        fn = W.nodal(lambda x, y: -W.SineSolution().laplacian(x, y), xc, yc)
+    else:
+        fn = W.random_nodal(shape, cfg.bc, W.SEED_RHS)
+    f_nodal = torch.tensor(fn, dtype=torch.float64, device="cuda")
+    b = s.zeros()
+    s.mass(f_nodal, b)
+    u0 = torch.tensor(W.random_guess(shape, cfg.bc, W.SEED_U0), dtype=torch.float64,
+                      device="cuda")
+    return cfg, s, b, u0, fn, NU
+
+
+def fdm_work(s, cfg):
+    """Algorithmic flops and bytes of one finest-level Schwarz-kernel launch:
+    per element 8 m^3 + 3 m^2 flops (four m x m x m contractions, eigenvalue
+    scaling, weighting); bytes: read r, read and write u (3 words per node)."""
+    pl, no, rows, cols = s.level_info(s.L)
+    m = pl + 1 + 2 * no
+    n_el = cfg.nx * cfg.ny
+    flops = n_el * (8.0 * m ** 3 + 3.0 * m ** 2)
+    return flops, m
+
+
+def cpu_baseline(cfg, fn, NU, budget_s: float = 12.0):
+    """Oracle MGCG(1,0) solves of the same workload until the budget is used
+    (at least one); DOF/s per V-cycle like the GPU value."""
+    import numpy as np
+    from oracle.mgcg import mgcg
+    from oracle.multigrid import Multigrid
+    from paper_1512_02390_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    mg = Multigrid(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, NU=NU)
+    sp = mg.spaces[-1]
+    F = sp.mass(fn)
+    U0 = W.random_guess(sp.shape, cfg.bc, W.SEED_U0)
+    n = int(sp.mask.sum())
+    t0 = time.perf_counter()
+    solves, cycles, its = 0, 0, 0
+    while True:
+        _, hist, it = mgcg(mg, U0, F, 200, 1e-10)
+        solves += 1
+        cycles += it
+        its = it
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * cycles / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{solves} full MGCG(1,0) solve(s) to 1e-10 of the same workload "
+                      f"({its} iterations each), {dt:.1f} s; time to 1e-10 "
+                      f"{1e3 * dt / solves:.0f} ms per solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--n-o", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--imax", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1512_02390_amd.sem import FP64, MIXED_FP32
+
+    torch.cuda.set_device(0)
+    prec = FP64 if args.precision == "fp64" else MIXED_FP32
+    cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec)
+    pl, no, rows, cols = s.level_info(s.L)
+    n_dof = (cfg.nx * cfg.p - 1) * (cfg.ny * cfg.p - 1) if cfg.bc == 0 else cfg.nx * cfg.ny * cfg.p ** 2
+
+    # warm-up solves (also the convergence record)
+    for _ in range(max(args.warmup, 1)):
+        u = u0.clone()
+        it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10)
+    if not ok:
+        raise SystemExit(f"MGCG did not reach 1e-10 in {args.imax} iterations")
+    r_bar = math.log10(hist[0] / hist[-1]) / it
+
+    # one private copy of the initial guess per timed step: no copies inside
+    us = [u0.clone() for _ in range(args.steps)]
+    s.timing_enable(s.L, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = 0
+    for k in range(args.steps):
+        it_k, _, ok_k = s.pcg_solve(us[k], b, args.imax, 1e-10)
+        cycles += it_k
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nk, kms = s.timing_read()
+    s.timing_enable(s.L, False)
+    dt = t1 - t0
+
+    # pure V-cycle throughput (MG(1,0) cycles on the iterate), for reference
+    uv = u0.clone()
+    for _ in range(3):
+        s.vcycle(uv, b)
+    torch.cuda.synchronize()
+    nv = 50
+    tv0 = time.perf_counter()
+    for _ in range(nv):
+        s.vcycle(uv, b)
+    torch.cuda.synchronize()
+    tv = (time.perf_counter() - tv0) / nv
+
+    flops, m = fdm_work(s, cfg)
+    word = 8 if prec == FP64 else 4
+    nbytes = 3.0 * rows * cols * word
+    avg_ms = kms / max(nk, 1)
+    ai = flops / nbytes
+    ridge = RIDGE_FP64 if prec == FP64 else RIDGE_FP32
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            rec = json.load(open(TRAFFIC_FILE))
+            key = f"{args.workload}_n{args.n_o}_{args.precision}"
+            if rec.get("source_hash") == kernel_source_hash() and key in rec.get("per_launch", {}):
+                traffic = rec["per_launch"][key]
+        except Exception:
+            traffic = None
+    if ai < ridge:
+        roof = {"bound": "hbm", "achieved": nbytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        peak = FP64_PEAK_TFS if prec == FP64 else FP32_PEAK_TFS
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof.update({"kernel": f"k_fdm<{'double' if prec == FP64 else 'float'},{m}>",
+                 "avg_launch_ms": avg_ms, "launches": nk,
+                 "algorithmic_flops": flops, "algorithmic_bytes": nbytes,
+                 "achieved_tflops": flops / (avg_ms * 1e-3) / 1e12})
+
+    out = {
+        "metric": "DOF/s per V-cycle + time to 1e-10 residual, mixed/learned vs plain FP64",
+        "value": n_dof * cycles / dt,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.description, "name": cfg.name, "elements": [cfg.nx, cfg.ny],
+                   "p": cfg.p, "dof": n_dof, "solver": "MGCG(1,0), w_5",
+                   "overlap": [s.level_info(l)[1] for l in range(1, s.L + 1)],
+                   "precision": args.precision, "rtol": 1e-10},
+        "time_to_1e-10_ms": 1e3 * dt / args.steps,
+        "iterations": it,
+        "r_bar": r_bar,
+        "vcycle_ms": 1e3 * tv,
+        "vcycle_dof_per_s": n_dof / tv,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, fn, NU)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
