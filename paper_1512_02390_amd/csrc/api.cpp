@@ -79,7 +79,7 @@ struct Tables {
   T *sx = nullptr, *sy = nullptr, *mx = nullptr, *my = nullptr;
   T *Sx = nullptr, *SxT = nullptr, *SyW = nullptr, *SyT = nullptr, *dinv = nullptr;
   T *wx = nullptr, *nuinv = nullptr, *nu = nullptr, *DT = nullptr;
-  T *E = nullptr;  // prolongation from level l-1
+  T *E = nullptr, *ET = nullptr;  // interpolation from level l-1 and its transpose
 };
 
 // Host description of the subdomain types along one direction.
@@ -100,8 +100,8 @@ struct Level {
   FdmTask *tasks = nullptr;
   int ntasks = 0, ntx = 0, nty = 0;
   // level vectors (FP64 and FP32)
-  double *u = nullptr, *f = nullptr, *r = nullptr, *t = nullptr;
-  float *uf = nullptr, *ff = nullptr, *rf = nullptr, *tf_ = nullptr;
+  double *u = nullptr, *f = nullptr, *r = nullptr;
+  float *uf = nullptr, *ff = nullptr, *rf = nullptr;
   long n() const { return (long)g.rows * g.cols; }
 };
 
@@ -313,7 +313,14 @@ void upload_tables(sem_ctx *h, Level &L, Tables<T> &t, const std::vector<double>
   }
   if (!nuinv.empty()) t.nuinv = upload<T>(P, nuinv);
   if (!L.nu_host.empty()) t.nu = upload<T>(P, L.nu_host);
-  if (!E.empty()) t.E = upload<T>(P, E);
+  if (!E.empty()) {
+    t.E = upload<T>(P, E);
+    const int nr = L.p + 1, nc = (int)(E.size() / nr);
+    std::vector<double> ET(E.size());
+    for (int a = 0; a < nr; ++a)
+      for (int c = 0; c < nc; ++c) ET[(size_t)c * nr + a] = E[(size_t)a * nc + c];
+    t.ET = upload<T>(P, ET);
+  }
 }
 
 std::vector<double> flat(const Mat &M) { return M.a; }
@@ -538,22 +545,15 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
                            l > 0 ? &fy : nullptr, dinv, ninv, E);
     // vectors
     const long n = lv.n();
-    long tn = 0;
-    if (l > 0) {
-      const Level &c = h->lev[l - 1];
-      tn = std::max((long)lv.g.rows * c.g.cols, (long)c.g.rows * lv.g.cols);
-    }
     if (l < L) {
       lv.u = dalloc<double>(h->pool, n);
       lv.f = dalloc<double>(h->pool, n);
     }
     lv.r = dalloc<double>(h->pool, n);
-    if (tn) lv.t = dalloc<double>(h->pool, tn);
     if (mixed) {
       lv.uf = dalloc<float>(h->pool, n);
       lv.ff = dalloc<float>(h->pool, n);
       lv.rf = dalloc<float>(h->pool, n);
-      if (tn) lv.tf_ = dalloc<float>(h->pool, tn);
     }
   }
   // coarse solver (level 0, p = 1)
@@ -688,25 +688,18 @@ void smooth(sem_ctx *h, int l, T *u, const T *f, T *rbuf, int n_it, bool u_is_ze
   }
 }
 
+// f_c = I_l^T r_f; uc_zero (optional) is cleared in the same pass.
 template <typename T>
-void restrict_(sem_ctx *h, int l, const T *rf, T *fc, T *tmp) {
+void restrict_(sem_ctx *h, int l, const T *rf, T *fc, T *uc_zero) {
   Level &F = h->lev[l], &C = h->lev[l - 1];
-  const Tables<T> &t = tabs<T>(F);
-  // x pass: fine rows x coarse cols, then y pass: coarse rows x coarse cols
-  launch_transfer<T>(0, 1, 0, rf, F.g.rows, F.g.cols, tmp, F.g.rows, C.g.cols, F.g.nx, F.p, C.p,
-                     F.g.periodic, t.E, h->stream);
-  launch_transfer<T>(1, 1, 0, tmp, F.g.rows, C.g.cols, fc, C.g.rows, C.g.cols, F.g.ny, F.p, C.p,
-                     F.g.periodic, t.E, h->stream);
+  launch_restrict<T>(F.g, C.g, rf, fc, uc_zero, tabs<T>(F).ET, h->stream);
 }
 
+// u_f += I_l u_c
 template <typename T>
-void prolong_add(sem_ctx *h, int l, const T *uc, T *uf, T *tmp) {
+void prolong_add(sem_ctx *h, int l, const T *uc, T *uf) {
   Level &F = h->lev[l], &C = h->lev[l - 1];
-  const Tables<T> &t = tabs<T>(F);
-  launch_transfer<T>(0, 0, 0, uc, C.g.rows, C.g.cols, tmp, C.g.rows, F.g.cols, F.g.nx, F.p, C.p,
-                     F.g.periodic, t.E, h->stream);
-  launch_transfer<T>(1, 0, 1, tmp, C.g.rows, F.g.cols, uf, F.g.rows, F.g.cols, F.g.ny, F.p, C.p,
-                     F.g.periodic, t.E, h->stream);
+  launch_prolong<T>(F.g, C.g, uc, uf, tabs<T>(F).E, h->stream);
 }
 
 // u0 = A_0^+ f0 in FP64.
@@ -752,14 +745,12 @@ struct LevelVecs {
   static T *u(Level &L) { return L.u; }
   static T *f(Level &L) { return L.f; }
   static T *r(Level &L) { return L.r; }
-  static T *t(Level &L) { return L.t; }
 };
 template <>
 struct LevelVecs<float> {
   static float *u(Level &L) { return L.uf; }
   static float *f(Level &L) { return L.ff; }
   static float *r(Level &L) { return L.rf; }
-  static float *t(Level &L) { return L.tf_; }
 };
 
 // Algorithm 3 on arrays of precision T.  uL/fL are the top-level arrays;
@@ -775,11 +766,8 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
   f[L] = fL;
   for (int l = L; l >= 1; --l) {
     Level &lv = h->lev[l];
-    const bool zero = (l < L) || u_zero;
-    if (l < L) {
-      u[l] = V::u(lv);
-      launch_fill<T>(u[l], lv.n(), T(0), h->stream);
-    }
+    const bool zero = (l < L) || u_zero;  // u_l was cleared by the restriction above it
+    if (l < L) u[l] = V::u(lv);
     const int n1 = ns1 ? ns1[l] : 1;
     smooth<T>(h, l, u[l], f[l], V::r(lv), n1, zero);
     const T *rr = f[l];
@@ -787,8 +775,9 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
       residual<T>(h, l, u[l], f[l], V::r(lv));
       rr = V::r(lv);
     }
-    T *fc = V::f(h->lev[l - 1]);
-    restrict_<T>(h, l, rr, fc, V::t(lv));
+    Level &cl = h->lev[l - 1];
+    T *fc = V::f(cl);
+    restrict_<T>(h, l, rr, fc, l - 1 > 0 ? V::u(cl) : nullptr);
     f[l - 1] = fc;
   }
   // with a single level (p = 1) the cycle is the coarse solve on the caller's array
@@ -797,7 +786,7 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
   for (int l = 1; l <= L; ++l) {
     Level &lv = h->lev[l];
     if (l < L) u[l] = V::u(lv);
-    prolong_add<T>(h, l, u[l - 1], u[l], V::t(lv));
+    prolong_add<T>(h, l, u[l - 1], u[l]);
     smooth<T>(h, l, u[l], f[l], V::r(lv), ns2 ? ns2[l] : 0, false);
   }
 }
@@ -934,12 +923,12 @@ sem_status sem_schwarz_smooth(sem_handle h, int32_t level, double *u, const doub
 
 sem_status sem_restrict(sem_handle h, int32_t level, const double *r_fine, double *f_coarse) {
   if (!h || !r_fine || !f_coarse || level < 1 || level >= (int)h->lev.size()) return SEM_EINVAL;
-  return guard(h, [&] { restrict_<double>(h, level, r_fine, f_coarse, h->lev[level].t); });
+  return guard(h, [&] { restrict_<double>(h, level, r_fine, f_coarse, nullptr); });
 }
 
 sem_status sem_prolong_add(sem_handle h, int32_t level, const double *u_coarse, double *u_fine) {
   if (!h || !u_coarse || !u_fine || level < 1 || level >= (int)h->lev.size()) return SEM_EINVAL;
-  return guard(h, [&] { prolong_add<double>(h, level, u_coarse, u_fine, h->lev[level].t); });
+  return guard(h, [&] { prolong_add<double>(h, level, u_coarse, u_fine); });
 }
 
 sem_status sem_coarse_solve(sem_handle h, const double *f0, double *u0) {

@@ -58,13 +58,15 @@ void launch_residual(const ResidualArgs<T> &a, hipStream_t s);
 template <typename T>
 void launch_fdm(const FdmArgs<T> &a, hipStream_t s);
 
-// 1-D transfer pass along x (dir = 0) or y (dir = 1).  mode 0: prolongation
-// out (+)= E in; mode 1: restriction out = E^T in with each shared fine node
-// counted once.  E is (pf+1) x (pc+1).
+// Transfers between level l-1 (order pc = ceil(pf/2)) and level l (order pf),
+// Section 3.2.  Restriction fc = I^T rf (each fine node counted once), also
+// zeroing uc_zero when non-null; prolongation uf += I uc.  E is the
+// (pf+1) x (pc+1) interpolation matrix, ET its transpose.
 template <typename T>
-void launch_transfer(int dir, int mode, int accumulate, const T *in, int in_rows, int in_cols,
-                     T *out, int out_rows, int out_cols, int n_el, int pf, int pc, int periodic,
-                     const T *E, hipStream_t s);
+void launch_restrict(const Grid &gf, const Grid &gc, const T *rf, T *fc, T *uc_zero, const T *ET,
+                     hipStream_t s);
+template <typename T>
+void launch_prolong(const Grid &gf, const Grid &gc, const T *uc, T *uf, const T *E, hipStream_t s);
 
 // C(M x N) = op(A) op(B) on strided views, optional elementwise scale by S
 // (same shape as C, leading dimension lds); C has leading dimension ldc.

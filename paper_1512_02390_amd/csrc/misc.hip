@@ -1,56 +1,9 @@
-// Transfers between p-levels (Section 3.2), the coarse-grid solve and the
-// vector kernels of the multigrid-preconditioned CG (Section 3.3).
+// The coarse-grid solve and the vector kernels of the multigrid-preconditioned CG (Section 3.3).
 #include "common.h"
 #include "kernels.h"
 
 namespace sem {
 namespace {
-
-// ---------------------------------------------------------------------------
-// 1-D transfer along one direction, one thread per output node.
-//   prolongation (mode 0): out[I] = sum_c E[a][c] in[e pc + c], with e, a the
-//     element and local index of fine node I;
-//   restriction  (mode 1): out[J] = sum_a E[a][g] in[e pf + a] (+ the left
-//     element's interior nodes when J is an element boundary node), i.e. the
-//     transpose of the assembled prolongation, each fine node counted once.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_transfer(int dir, int mode, int acc, int zero_bnd, const T *__restrict__ in,
-                           int in_rows, int in_cols, T *__restrict__ out, int out_rows,
-                           int out_cols, int n_el, int pf, int pc, int periodic,
-                           const T *__restrict__ E) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)out_rows * out_cols) return;
-  const int orow = (int)(idx / out_cols), ocol = (int)(idx - (long)orow * out_cols);
-  if (zero_bnd && !periodic &&
-      (orow == 0 || ocol == 0 || orow == out_rows - 1 || ocol == out_cols - 1)) {
-    if (!acc) out[idx] = T(0);
-    return;
-  }
-  const int I = dir == 0 ? ocol : orow;
-  const int other = dir == 0 ? orow : ocol;
-  const int nin = dir == 0 ? in_cols : in_rows;
-  auto IN = [&](int k) -> T {
-    if (periodic) k = wrap(k, nin);
-    return dir == 0 ? in[(long)other * in_cols + k] : in[(long)k * in_cols + other];
-  };
-  T v = T(0);
-  const int ldE = pc + 1;
-  if (mode == 0) {
-    const int e = min(I / pf, n_el - 1);
-    const int a = I - e * pf;
-    for (int c = 0; c <= pc; ++c) v = fma(E[a * ldE + c], IN(e * pc + c), v);
-  } else {
-    const int e = min(I / pc, n_el - 1);
-    const int gl = I - e * pc;
-    for (int a = 0; a <= pf; ++a) v = fma(E[a * ldE + gl], IN(e * pf + a), v);
-    if (gl == 0 && (periodic || e > 0)) {
-      const int em = periodic ? wrap(e - 1, n_el) : e - 1;
-      for (int a = 0; a < pf; ++a) v = fma(E[a * ldE + pc], IN(em * pf + a), v);
-    }
-  }
-  out[idx] = acc ? out[idx] + v : v;
-}
 
 // ---------------------------------------------------------------------------
 // Small dense GEMM (coarse fast diagonalisation), 16x16 tiles.
@@ -260,23 +213,6 @@ int red_blocks(long n) {
 }
 
 }  // namespace
-
-template <typename T>
-void launch_transfer(int dir, int mode, int accumulate, const T *in, int in_rows, int in_cols,
-                     T *out, int out_rows, int out_cols, int n_el, int pf, int pc, int periodic,
-                     const T *E, hipStream_t s) {
-  const long n = (long)out_rows * out_cols;
-  // the last pass of a transfer writes the final level array: keep its
-  // Dirichlet boundary at zero
-  const int zero_bnd = (dir == 1);
-  hipLaunchKernelGGL(k_transfer<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, dir, mode,
-                     accumulate, zero_bnd, in, in_rows, in_cols, out, out_rows, out_cols, n_el, pf,
-                     pc, periodic, E);
-}
-template void launch_transfer<double>(int, int, int, const double *, int, int, double *, int, int,
-                                      int, int, int, int, const double *, hipStream_t);
-template void launch_transfer<float>(int, int, int, const float *, int, int, float *, int, int,
-                                     int, int, int, int, const float *, hipStream_t);
 
 void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const double *B,
                  long brs, long bcs, double *C, long ldc, const double *S, long lds,
