@@ -90,7 +90,7 @@ def fdm_work(s, cfg):
     return flops, m
 
 
-def cpu_baseline(cfg, fn, NU, budget_s: float = 12.0):
+def cpu_baseline(cfg, fn, NU, ns1, ns2, budget_s: float = 12.0):
     """Oracle MGCG(1,0) solves of the same workload until the budget is used
     (at least one); DOF/s per V-cycle like the GPU value."""
     import numpy as np
@@ -110,7 +110,7 @@ def cpu_baseline(cfg, fn, NU, budget_s: float = 12.0):
     t0 = time.perf_counter()
     solves, cycles, its = 0, 0, 0
     while True:
-        _, hist, it = mgcg(mg, U0, F, 200, 1e-10)
+        _, hist, it = mgcg(mg, U0, F, 200, 1e-10, ns1, ns2)
         solves += 1
         cycles += it
         its = it
@@ -118,7 +118,7 @@ def cpu_baseline(cfg, fn, NU, budget_s: float = 12.0):
             break
     dt = time.perf_counter() - t0
     return {"value": n * cycles / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{solves} full MGCG(1,0) solve(s) to 1e-10 of the same workload "
+            "sample": f"{solves} full MGCG solve(s) to 1e-10 of the same workload "
                       f"({its} iterations each), {dt:.1f} s; time to 1e-10 "
                       f"{1e3 * dt / solves:.0f} ms per solve"}
 
@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--n-o", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--imax", type=int, default=200)
+    ap.add_argument("--cycle", default=None, choices=["mg10", "mg11", "var11"],
+                    help="smoothing schedule (default: mg10; mg11 for variable nu)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -146,13 +148,22 @@ def main():
     torch.cuda.set_device(0)
     prec = FP64 if args.precision == "fp64" else MIXED_FP32
     cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec)
+    cycle = args.cycle or ("mg11" if cfg.variable_nu else "mg10")
+    L = s.L
+    if cycle == "mg10":
+        ns1, ns2 = [1] * (L + 1), [0] * (L + 1)
+    elif cycle == "mg11":
+        ns1, ns2 = [1] * (L + 1), [1] * (L + 1)
+    else:
+        ns1 = [2 ** (L - l) for l in range(L + 1)]
+        ns2 = list(ns1)
     pl, no, rows, cols = s.level_info(s.L)
     n_dof = (cfg.nx * cfg.p - 1) * (cfg.ny * cfg.p - 1) if cfg.bc == 0 else cfg.nx * cfg.ny * cfg.p ** 2
 
     # warm-up solves (also the convergence record)
     for _ in range(max(args.warmup, 1)):
         u = u0.clone()
-        it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10)
+        it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10, ns1, ns2)
     if not ok:
         raise SystemExit(f"MGCG did not reach 1e-10 in {args.imax} iterations")
     r_bar = math.log10(hist[0] / hist[-1]) / it
@@ -164,7 +175,7 @@ def main():
     t0 = time.perf_counter()
     cycles = 0
     for k in range(args.steps):
-        it_k, _, ok_k = s.pcg_solve(us[k], b, args.imax, 1e-10)
+        it_k, _, ok_k = s.pcg_solve(us[k], b, args.imax, 1e-10, ns1, ns2)
         cycles += it_k
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -175,12 +186,12 @@ def main():
     # pure V-cycle throughput (MG(1,0) cycles on the iterate), for reference
     uv = u0.clone()
     for _ in range(3):
-        s.vcycle(uv, b)
+        s.vcycle(uv, b, ns1, ns2)
     torch.cuda.synchronize()
     nv = 50
     tv0 = time.perf_counter()
     for _ in range(nv):
-        s.vcycle(uv, b)
+        s.vcycle(uv, b, ns1, ns2)
     torch.cuda.synchronize()
     tv = (time.perf_counter() - tv0) / nv
 
@@ -227,7 +238,7 @@ def main():
         "dtype": "f64" if prec == FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": cfg.description, "name": cfg.name, "elements": [cfg.nx, cfg.ny],
-                   "p": cfg.p, "dof": n_dof, "solver": "MGCG(1,0), w_5",
+                   "p": cfg.p, "dof": n_dof, "solver": f"MGCG {cycle}, w_5",
                    "overlap": [s.level_info(l)[1] for l in range(1, s.L + 1)],
                    "precision": args.precision, "rtol": 1e-10},
         "time_to_1e-10_ms": 1e3 * dt / args.steps,
@@ -238,7 +249,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, fn, NU)
+        out["cpu_baseline"] = cpu_baseline(cfg, fn, NU, ns1, ns2)
     print(json.dumps(out), flush=True)
 
 

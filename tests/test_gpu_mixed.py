@@ -1,0 +1,84 @@
+"""Mixed precision (FP32 V-cycle inside FP64 residual and CG): error against
+the FP64 oracle, stated per result.
+
+  - one mixed V-cycle u <- u + MG32(0, f - A u) differs from the oracle's FP64
+    V-cycle by FP32 rounding only: relative error below 2e-5;
+  - mixed MGCG reaches a true FP64 residual of 1e-10 (recomputed by the
+    oracle), in at most two iterations more than FP64, and its solution
+    matches the oracle's FP64 solution (solved to 1e-13) to 1e-8 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from parity_cases import CASES, P, build_gpu, build_oracle, rel_err
+from paper_1512_02390_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MIXED = 1
+SUBSET = [c for c in CASES if c.name in ("dir_p4_no1", "dir_p8_no3_stretch", "per_p6_no2_cubic",
+                                         "dir_p16_ceil8", "dir_p12_ceil8_varnu_stretch",
+                                         "dir_p32_ceil8")]
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=SUBSET, ids=lambda c: c.name)
+def pair(request):
+    case = request.param
+    print(f"[gpu-mixed] {case.name}", flush=True)
+    mg, NU = build_oracle(case)
+    gpu = build_gpu(case, NU, precision=MIXED)
+    yield case, mg, gpu
+    gpu.close()
+
+
+def test_mixed_vcycle_error(pair):
+    case, mg, gpu = pair
+    sp = mg.spaces[-1]
+    U = W.random_guess(sp.shape, case.bc, 90)
+    F = W.random_nodal(sp.shape, case.bc, 91)
+    if case.bc == P:
+        F = np.where(sp.mask, F - F[sp.mask].mean(), 0.0)
+    ref = mg.vcycle(U, F)
+    u = _dev(U)
+    gpu.vcycle(u, _dev(F))
+    err = rel_err(_host(u), ref)
+    print(f"  mixed V-cycle rel. error vs FP64 oracle: {err:.2e}")
+    assert err < 2e-5
+
+
+def test_mixed_pcg_reaches_fp64_accuracy(pair):
+    case, mg, gpu = pair
+    from oracle.mgcg import mgcg
+    sp = mg.spaces[-1]
+    U0 = W.random_guess(sp.shape, case.bc, 92)
+    F = W.random_nodal(sp.shape, case.bc, 93)
+    Uref, hist_ref, it_ref = mgcg(mg, U0, F, 100, 1e-13)
+    _, _, it64 = mgcg(mg, U0, F, 100, 1e-10)
+    u = _dev(U0)
+    it, hist, ok = gpu.pcg_solve(u, _dev(F), 100, 1e-10)
+    assert ok
+    Ug = _host(u)
+    Fp = F - (F[sp.mask].mean() if case.bc == P else 0.0)
+    r0 = np.linalg.norm(mg.residual(mg.L, U0, sp.zero_boundary(Fp))[sp.mask])
+    r = np.linalg.norm(mg.residual(mg.L, Ug, sp.zero_boundary(Fp))[sp.mask])
+    if case.bc == P:
+        Ug = Ug - Ug.mean()
+        Uref = Uref - Uref.mean()
+    err = rel_err(Ug, Uref)
+    print(f"  mixed MGCG: {it} iterations (FP64 oracle {it64}), true residual ratio "
+          f"{r / r0:.2e}, rel. error vs FP64 solution {err:.2e}")
+    assert r <= 2e-10 * r0
+    assert it <= it64 + 2
+    assert err < 1e-8
