@@ -46,13 +46,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_problem(name: str, n_o: int, precision: int):
+RULES = {"fixed": 0, "ceil8": 1, "floor8": 2, "ceil2": 3}
+
+
+def make_problem(name: str, n_o: int, precision: int, rule=None, overlaps=None):
     import numpy as np
     import torch
     from paper_1512_02390_amd import workloads as W
     from paper_1512_02390_amd.sem import Solver
 
     cfg = W.config(name, n_o)
+    if rule is not None:
+        cfg.overlap_rule = RULES[rule]
+    if overlaps is not None:
+        cfg.overlaps = overlaps
     nu = None
     NU = None
     if cfg.variable_nu:
@@ -64,7 +71,7 @@ def make_problem(name: str, n_o: int, precision: int):
         probe.close()
         NU = W.nodal(nu.nu, xc, yc)
     s = Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
-               precision=precision)
+               precision=precision, overlaps=cfg.overlaps)
     shape = s.shape()
     if name == "c1":
         xc, yc = s.node_coords()
@@ -102,7 +109,8 @@ def cpu_baseline(cfg, fn, NU, ns1, ns2, budget_s: float = 12.0):
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    mg = Multigrid(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, NU=NU)
+    mg = Multigrid(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, NU=NU,
+                   overlaps=cfg.overlaps)
     sp = mg.spaces[-1]
     F = sp.mass(fn)
     U0 = W.random_guess(sp.shape, cfg.bc, W.SEED_U0)
@@ -130,6 +138,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--n-o", type=int, default=1)
+    ap.add_argument("--rule", default=None, choices=sorted(RULES),
+                    help="overlap rule per level (default: the workload's)")
+    ap.add_argument("--overlaps", default=None,
+                    help="explicit overlaps of levels 1..L, comma separated")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--imax", type=int, default=200)
     ap.add_argument("--cycle", default=None, choices=["mg10", "mg11", "var11"],
@@ -147,7 +159,10 @@ def main():
 
     torch.cuda.set_device(0)
     prec = FP64 if args.precision == "fp64" else MIXED_FP32
-    cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec)
+    ovl = None
+    if args.overlaps:
+        ovl = [0] + [int(v) for v in args.overlaps.split(",")]
+    cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec, args.rule, ovl)
     cycle = args.cycle or ("mg11" if cfg.variable_nu else "mg10")
     L = s.L
     if cycle == "mg10":

@@ -72,6 +72,10 @@ typedef struct {
 typedef struct {
   int32_t rule;            /* sem_overlap_rule */
   int32_t n_o;             /* used by SEM_NO_FIXED */
+  /* Optional host array of L+1 overlaps indexed by level (entry 0 unused);
+   * when non-NULL it replaces the rule.  Each entry must lie in
+   * [0, p_l - 1]; L+1 is the number of levels, ceil-halving p down to 1. */
+  const int32_t *per_level;
 } sem_overlap;
 
 typedef struct {

@@ -79,12 +79,16 @@ def interpolate_nodal(space_from: Space, space_to: Space, V) -> np.ndarray:
 
 class Multigrid:
     def __init__(self, xb, yb, p: int, bc: int, overlap_rule: int = OVERLAP_FIXED,
-                 n_o: int = 1, wf: int = 5, NU=None, alpha_x=None, alpha_y=None):
+                 n_o: int = 1, wf: int = 5, NU=None, alpha_x=None, alpha_y=None, overlaps=None):
+        """overlaps: optional explicit n_o per level (index 0 unused)."""
         self.orders = level_orders(p)
         self.L = len(self.orders) - 1
         self.bc = bc
         self.spaces = [Space(xb, yb, q, bc) for q in self.orders]
-        self.overlaps = [0] + [level_overlap(overlap_rule, n_o, q) for q in self.orders[1:]]
+        if overlaps is not None:
+            self.overlaps = [0] + [int(v) for v in overlaps[1:]]
+        else:
+            self.overlaps = [0] + [level_overlap(overlap_rule, n_o, q) for q in self.orders[1:]]
         self.P = [None] + [
             (sps.csr_matrix(prolongation_1d(self.spaces[l - 1].ax, self.spaces[l].ax)),
              sps.csr_matrix(prolongation_1d(self.spaces[l - 1].ay, self.spaces[l].ay)))

@@ -405,7 +405,14 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   for (int l = 0; l <= L; ++l) {
     Level &lv = h->lev[l];
     lv.p = orders[l];
-    lv.n_o = l == 0 ? 0 : level_overlap(ov->rule, ov->n_o, lv.p);
+    if (l == 0) {
+      lv.n_o = 0;
+    } else if (ov->per_level) {
+      lv.n_o = ov->per_level[l];
+      if (lv.n_o < 0 || lv.n_o > lv.p - 1) throw Fail{SEM_EINVAL, "per-level overlap outside [0, p_l - 1]"};
+    } else {
+      lv.n_o = level_overlap(ov->rule, ov->n_o, lv.p);
+    }
     lv.m = lv.p + 1 + 2 * lv.n_o;
     if (l > 0 && lv.m > kMaxTile) throw Fail{SEM_EUNSUP, "subdomain width p+1+2n_o above 48"};
     lv.g = Grid{nx, ny, lv.p, per ? ny * lv.p : ny * lv.p + 1, per ? nx * lv.p : nx * lv.p + 1, per};

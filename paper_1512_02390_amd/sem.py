@@ -41,7 +41,7 @@ class _Mesh(C.Structure):
 
 
 class _Overlap(C.Structure):
-    _fields_ = [("rule", C.c_int32), ("n_o", C.c_int32)]
+    _fields_ = [("rule", C.c_int32), ("n_o", C.c_int32), ("per_level", C.POINTER(C.c_int32))]
 
 
 class _Weights(C.Structure):
@@ -111,7 +111,7 @@ class Solver:
 
     def __init__(self, xb, yb, p: int, bc: int = BC_DIRICHLET, overlap_rule: int = NO_FIXED,
                  n_o: int = 1, wf: int = 5, nu=None, precision: int = FP64, alpha_x=None,
-                 alpha_y=None, stream=None):
+                 alpha_y=None, stream=None, overlaps=None):
         import torch
         self.lib = load_library()
         self.torch = torch
@@ -120,7 +120,8 @@ class Solver:
         dp = C.POINTER(C.c_double)
         mesh = _Mesh(len(self._xb) - 1, len(self._yb) - 1, self._xb.ctypes.data_as(dp),
                      self._yb.ctypes.data_as(dp), bc)
-        ov = _Overlap(overlap_rule, n_o)
+        self._ovl = None if overlaps is None else _i32_array(overlaps)
+        ov = _Overlap(overlap_rule, n_o, self._ovl)
         self._ax = None if alpha_x is None else np.ascontiguousarray(alpha_x, dtype=np.float64)
         self._ay = None if alpha_y is None else np.ascontiguousarray(alpha_y, dtype=np.float64)
         wts = _Weights(wf, None if self._ax is None else self._ax.ctypes.data_as(dp),

@@ -13,7 +13,10 @@ meshes of rectangular elements.  The named configurations are:
   c2  Poisson, [0,1]^2, 64x64 uniform elements, p=8, Dirichlet, random RHS.
   c3  Poisson, [0,1]^2, 128x128 uniform elements, p=16, Dirichlet, random RHS.
   c4  Variable diffusion, 32x32 elements, x widths growing geometrically to an
-      aspect ratio of 16, p=12, nu = exp(g) with g a Gaussian random field.
+      aspect ratio of 16, p=12, nu = exp(g) with g a Gaussian random field
+      (sigma = 1, correlation length 1.0: with the x-stretched elements a
+      shorter correlation length leaves nu unresolved by the element means
+      and the method diverges).
   c5  As c4 on 48x48 elements with p=32.
 """
 from __future__ import annotations
@@ -137,13 +140,13 @@ class PaperNu:
 
 @dataclass
 class GaussianFieldNu:
-    """nu = exp(g), g a stationary Gaussian field with unit variance and
+    """nu = exp(g), g a stationary Gaussian field with variance sigma^2 and
     squared-exponential covariance exp(-|d|^2 / (2 ell^2)), represented by K
     random Fourier features: g = sqrt(2/K) sum_k cos(w_k . x + phi_k) with
     w_k ~ N(0, ell^-2 I) and phi_k ~ U[0, 2 pi).  Analytic everywhere, so every
     multigrid level can evaluate it at its own nodes."""
     seed: int = SEED_GRF
-    ell: float = 0.1
+    ell: float = 1.0
     sigma: float = 1.0
     K: int = 1024
     omega: np.ndarray = field(init=False, repr=False)
@@ -202,6 +205,7 @@ class Config:
     n_o: int               # used when overlap_rule == 0
     variable_nu: bool
     description: str
+    overlaps: list | None = None   # explicit n_o per level (entry 0 unused)
 
 
 OVERLAP_FIXED, OVERLAP_CEIL8, OVERLAP_FLOOR8, OVERLAP_CEIL2 = 0, 1, 2, 3

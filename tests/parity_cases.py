@@ -25,6 +25,7 @@ class Case:
     n_o: int = 1
     wf: int = 5
     varnu: bool = False
+    overlaps: tuple | None = None   # explicit n_o per level (entry 0 unused)
 
     def breaks(self):
         if self.stretched:
@@ -49,6 +50,9 @@ CASES = [
     Case("per_p8_varnu", 3, 4, 8, P, rule=CEIL8, varnu=True),
     Case("dir_p7_no6_linear_stretch", 3, 2, 7, D, stretched=True, n_o=6, wf=1),
     Case("dir_single_element_p9", 1, 1, 9, D, n_o=3),
+    Case("dir_p12_ceil2_varnu_stretch", 4, 3, 12, D, stretched=True, rule=CEIL2, varnu=True),
+    Case("dir_p32_levels_varnu_stretch", 2, 2, 32, D, stretched=True, varnu=True,
+         overlaps=(0, 1, 1, 2, 4, 7)),
 ]
 
 
@@ -65,14 +69,15 @@ def build_oracle(case: Case):
     if nu is not None:
         top = Space(xb, yb, case.p, case.bc)
         NU = W.nodal(nu.nu, top.x(), top.y())
-    return Multigrid(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, NU=NU), NU
+    return Multigrid(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, NU=NU,
+                     overlaps=case.overlaps), NU
 
 
 def build_gpu(case: Case, NU=None, precision=0):
     from paper_1512_02390_amd.sem import Solver
     xb, yb = case.breaks()
     return Solver(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, nu=NU,
-                  precision=precision)
+                  precision=precision, overlaps=case.overlaps)
 
 
 def rel_err(a, b) -> float:
