@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--cycle", default=None, choices=["mg10", "mg11", "var11"],
                     help="smoothing schedule (default: mg10; mg11 for variable nu)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the reference "
+                         "kernel for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -158,6 +161,15 @@ def main():
     from paper_1512_02390_amd.sem import FP64, MIXED_FP32
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     prec = FP64 if args.precision == "fp64" else MIXED_FP32
     ovl = None
     if args.overlaps:
