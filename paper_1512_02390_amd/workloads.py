@@ -232,3 +232,22 @@ def config(name: str, n_o: int = 1) -> Config:
                       uniform_breaks(n, 1.0), OVERLAP_CEIL8, 0, True,
                       f"variable nu=exp(GRF), {n}x{n} elements stretched to AR 16, p={p}")
     raise ValueError(name)
+
+
+# ----------------------------------------------------------------------------
+# Network initialisation for the learned-parameter extension (random numbers
+# only; the network arithmetic lives on each side).
+# ----------------------------------------------------------------------------
+
+def mlp_init(d_in: int = 8, width: int = 64, d_out: int = 2, seed: int = SEED_MLP) -> np.ndarray:
+    """Flat parameter vector W1, b1, W2, b2, W3, b3 (weights row-major, out x in):
+    weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero.  Values are
+    rounded to float32 so that FP32 and FP64 consumers start from the same
+    numbers."""
+    g = rng(seed)
+    parts = []
+    for fi, fo in ((d_in, width), (width, width), (width, d_out)):
+        b = math.sqrt(6.0 / (fi + fo))
+        parts.append(g.uniform(-b, b, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
