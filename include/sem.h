@@ -161,6 +161,67 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
 sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on);
 sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms);
 
+/* ------------------------------------------------------------------------
+ * Learned Schwarz parameters (a project extension; the paper fixes the
+ * weights of Section 3.1 and the overlap rules of Section 4 by hand).  A
+ * small network predicts, per element, a width scale alpha for the
+ * smoothed-sign weights and an overlap ratio from local features; the
+ * predictions are reduced to the per-grid-line width scales and per-level
+ * overlaps that sem_setup accepts (sem_weights.alpha_x / alpha_y,
+ * sem_overlap.per_level).
+ * ------------------------------------------------------------------------ */
+
+/* Features of every element e = ey * nx + ex of the finest level, 8 FP32
+ * values per element, written to the device array feat[n_e][8]:
+ *   0  log2(h_x / h_y)
+ *   1  ln nu_bar_e, the GLL-quadrature element mean of nu used by the local
+ *      solves (Section 4, variable diffusion); 0 for the Poisson problem
+ *   2-5  ln nu_bar of the left, right, lower and upper neighbour minus
+ *      ln nu_bar_e (0 where the side is a Dirichlet boundary)
+ *   6  ln(max nu / min nu) over the element's nodes
+ *   7  p / 32 */
+sem_status sem_elem_features(sem_handle h, float *feat);
+
+/* Multilayer perceptron d_in -> width -> width -> d_out with tanh hidden
+ * layers and logistic outputs, trained on the device with the loss
+ * 1/(2n) sum_s sum_o (y_so - t_so)^2 and Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected).  This build supports width = 64, d_in <= 16,
+ * d_out <= 4 (SEM_EUNSUP otherwise).  Parameters are one flat FP32 array:
+ * W1 (width x d_in, row-major), b1, W2 (width x width), b2, W3
+ * (d_out x width), b3. */
+typedef struct sem_mlp_ctx *sem_mlp;
+sem_status sem_mlp_num_params(int32_t d_in, int32_t width, int32_t d_out, int64_t *n);
+/* params: host array of the initial parameters (copied). */
+sem_status sem_mlp_create(int32_t d_in, int32_t width, int32_t d_out, const float *params,
+                          void *stream, sem_mlp *out);
+sem_status sem_mlp_destroy(sem_mlp m);
+/* y[n][d_out] = network(x[n][d_in]); device arrays, asynchronous. */
+sem_status sem_mlp_forward(sem_mlp m, const float *x, int64_t n, float *y);
+/* Gradient of the loss over the n samples (x[n][d_in], targets t[n][d_out],
+ * device) into the device array grad[num_params]; *loss (host, may be NULL)
+ * receives the loss and then the call synchronises.  Deterministic. */
+sem_status sem_mlp_gradient(sem_mlp m, const float *x, const float *t, int64_t n, float *grad,
+                            float *loss);
+/* One Adam step with learning rate lr on the full batch of n samples;
+ * *loss (may be NULL) receives the loss before the step (synchronises). */
+sem_status sem_mlp_train_step(sem_mlp m, const float *x, const float *t, int64_t n, float lr,
+                              float *loss);
+/* Host copy of the current parameters (synchronises). */
+sem_status sem_mlp_get_params(sem_mlp m, float *params);
+
+/* Host-side reduction of per-element predictions pred[n_e][2] = (alpha_e,
+ * q_e) (host array, e = ey * nx + ex) to setup parameters:
+ *   alpha_e clipped to [0.1, 1]; alpha_x[i] (nx+1 entries) and alpha_y[j]
+ *   (ny+1 entries) = mean of alpha_e over the elements touching grid line
+ *   i or j (periodic: the first and last line are one line);
+ *   rho = 0.5 mean_e q_e; overlaps[l] = ceil(rho p_l) clamped to
+ *   [1, p_l - 1] and to p_l + 1 + 2 n_o <= 48, for l = 1..L, overlaps[0] = 0
+ *   (L+1 entries, p_l ceil-halving from p to 1).
+ * A constant width scale along every grid line keeps the weights a partition
+ * of unity.  SEM_ENAN for non-finite predictions. */
+sem_status sem_learned_params(const float *pred, int32_t nx, int32_t ny, int32_t p, int32_t bc,
+                              int32_t *overlaps, double *alpha_x, double *alpha_y);
+
 /* Euclidean norm of the unknowns of a level-L array (synchronises). */
 sem_status sem_norm(sem_handle h, const double *x, double *out);
 

@@ -124,6 +124,8 @@ struct sem_ctx {
   // PCG / reductions
   double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr, *pro = nullptr;
   double *partial = nullptr, *scal = nullptr;  // scal: device scalars
+  // element widths and 1/nu_bar per element (element features)
+  double *hx = nullptr, *hy = nullptr, *enuinv = nullptr;
   // optional event timing of the Schwarz kernel on one level
   int time_level = -1;
   std::vector<hipEvent_t> ev;
@@ -396,6 +398,13 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   }
   h->bc = mesh->bc;
   h->varnu = nu != nullptr;
+  {
+    std::vector<double> wx(nx), wy(ny);
+    for (int e = 0; e < nx; ++e) wx[e] = xb[e + 1] - xb[e];
+    for (int e = 0; e < ny; ++e) wy[e] = yb[e + 1] - yb[e];
+    h->hx = upload<double>(h->pool, wx);
+    h->hy = upload<double>(h->pool, wy);
+  }
   // level orders p_L = p, p_{l-1} = ceil(p_l / 2)
   std::vector<int> orders{p};
   while (orders.back() > 1) orders.push_back((orders.back() + 1) / 2);
@@ -482,6 +491,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   }
   std::vector<double> nuinv;
   for (double v : nubar) nuinv.push_back(1.0 / v);
+  if (!nuinv.empty()) h->enuinv = upload<double>(h->pool, nuinv);
   const bool mixed = h->precision == SEM_MIXED_FP32;
   // per-level tables
   for (int l = 0; l <= L; ++l) {
@@ -1045,6 +1055,15 @@ sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms) {
     *count = (int64_t)(h->ev_used / 2);
     *total_ms = tot;
     h->ev_used = 0;
+  });
+}
+
+sem_status sem_elem_features(sem_handle h, float *feat) {
+  if (!h || !feat) return SEM_EINVAL;
+  return guard(h, [&] {
+    Level &top = h->lev.back();
+    launch_features(top.g, h->varnu ? top.td.nu : nullptr, h->enuinv, h->hx, h->hy, feat,
+                    h->stream);
   });
 }
 

@@ -112,3 +112,26 @@ void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s
 void launch_copy_scalar(const double *src, double *dst, hipStream_t s);
 
 }  // namespace sem
+
+namespace sem {
+
+// Learned Schwarz parameters (project extension): MLP d_in -> 64 -> 64 -> d_out.
+constexpr int kMlpMaxIn = 16;
+constexpr int kMlpMaxOut = 4;
+constexpr int kMlpFeatures = 8;   // features per element
+
+long mlp_num_params(int d_in, int d_out);
+// Forward (part == null) or forward + backward of the mean squared error
+// 1/(2n) sum (y - t)^2 over n samples; each of the nblk workgroups writes one
+// row of `stride` (>= np + 1) partial sums: the gradient, then the loss.
+void launch_mlp(const float *P, int d_in, int d_out, const float *X, const float *T, long n,
+                float *Y, float *part, long stride, int nblk, hipStream_t s);
+// Sums the partial rows; writes the gradient (if grad) and loss (if loss);
+// with adam != 0 updates P, m, v (c1, c2: bias corrections 1/(1-beta^t)).
+void launch_mlp_reduce(const float *part, int nblk, long stride, long np, float *grad, float *loss,
+                       float *P, float *m, float *v, float lr, float c1, float c2, int adam,
+                       hipStream_t s);
+void launch_features(const Grid &g, const double *nu, const double *nuinv, const double *hx,
+                     const double *hy, float *F, hipStream_t s);
+
+}  // namespace sem

@@ -26,7 +26,10 @@ STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EDOM", -3: "SEM_ENOMEM", -4: "
 EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_node_coords",
            "sem_mass", "sem_residual", "sem_schwarz_smooth", "sem_restrict", "sem_prolong_add",
            "sem_coarse_solve", "sem_vcycle", "sem_pcg_solve", "sem_norm", "sem_strerror",
-           "sem_last_error", "sem_timing_enable", "sem_timing_read"]
+           "sem_last_error", "sem_timing_enable", "sem_timing_read", "sem_elem_features",
+           "sem_mlp_num_params", "sem_mlp_create", "sem_mlp_destroy", "sem_mlp_forward",
+           "sem_mlp_gradient", "sem_mlp_train_step", "sem_mlp_get_params",
+           "sem_learned_params"]
 
 
 class SemError(RuntimeError):
@@ -80,6 +83,17 @@ def load_library(path: str = LIB_PATH):
     lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
     lib.sem_timing_enable.argtypes = [P, I32, I32]
     lib.sem_timing_read.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
+    F = C.POINTER(C.c_float)
+    lib.sem_elem_features.argtypes = [P, P]
+    lib.sem_mlp_num_params.argtypes = [I32, I32, I32, C.POINTER(I64)]
+    lib.sem_mlp_create.argtypes = [I32, I32, I32, F, P, C.POINTER(P)]
+    lib.sem_mlp_destroy.argtypes = [P]
+    lib.sem_mlp_forward.argtypes = [P, P, I64, P]
+    lib.sem_mlp_gradient.argtypes = [P, P, P, I64, P, F]
+    lib.sem_mlp_train_step.argtypes = [P, P, P, I64, C.c_float, F]
+    lib.sem_mlp_get_params.argtypes = [P, F]
+    lib.sem_learned_params.argtypes = [F, I32, I32, I32, I32, C.POINTER(I32), C.POINTER(D),
+                                       C.POINTER(D)]
     lib.sem_strerror.argtypes = [I32]
     lib.sem_strerror.restype = C.c_char_p
     lib.sem_last_error.argtypes = [P]
@@ -234,3 +248,95 @@ class Solver:
         out = C.c_double()
         self._check(self.lib.sem_norm(self.h, _ptr(x), C.byref(out)))
         return out.value
+
+    def elem_features(self):
+        """Device tensor (n_e, 8) of FP32 element features, e = ey * nx + ex."""
+        ne = (len(self._xb) - 1) * (len(self._yb) - 1)
+        out = self.torch.empty((ne, 8), dtype=self.torch.float32, device="cuda")
+        self._check(self.lib.sem_elem_features(self.h, _ptr(out)))
+        return out
+
+
+def _raise(st, what):
+    if st != 0:
+        raise SemError(st, what)
+
+
+class MLP:
+    """Device MLP d_in -> 64 -> 64 -> d_out (tanh, logistic output) trained with
+    the library's own forward / backward / Adam kernels."""
+
+    def __init__(self, params, d_in: int = 8, width: int = 64, d_out: int = 2, stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.d_in, self.width, self.d_out = d_in, width, d_out
+        n = C.c_int64()
+        _raise(self.lib.sem_mlp_num_params(d_in, width, d_out, C.byref(n)), "mlp dimensions")
+        self.np = n.value
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.np:
+            raise ValueError(f"expected {self.np} parameters, got {p.size}")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _raise(self.lib.sem_mlp_create(d_in, width, d_out, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                       C.c_void_p(stream), C.byref(h)), "sem_mlp_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sem_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, x):
+        y = self.torch.empty((x.shape[0], self.d_out), dtype=self.torch.float32, device="cuda")
+        _raise(self.lib.sem_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(y)), "sem_mlp_forward")
+        return y
+
+    def gradient(self, x, t):
+        """(loss, gradient as a device tensor)."""
+        g = self.torch.empty(self.np, dtype=self.torch.float32, device="cuda")
+        loss = C.c_float()
+        _raise(self.lib.sem_mlp_gradient(self.h, _ptr(x), _ptr(t), x.shape[0], _ptr(g),
+                                         C.byref(loss)), "sem_mlp_gradient")
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float, want_loss: bool = False):
+        loss = C.c_float()
+        _raise(self.lib.sem_mlp_train_step(self.h, _ptr(x), _ptr(t), x.shape[0], lr,
+                                           C.byref(loss) if want_loss else None),
+               "sem_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.np, dtype=np.float32)
+        _raise(self.lib.sem_mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))),
+               "sem_mlp_get_params")
+        return out
+
+
+def learned_params(pred, nx: int, ny: int, p: int, bc: int):
+    """Reduce per-element predictions (n_e, 2) = (alpha_e, q_e) to
+    (overlaps per level, alpha per x grid line, alpha per y grid line)."""
+    lib = load_library()
+    pr = np.ascontiguousarray(pred, dtype=np.float32).reshape(-1)
+    levels = 1
+    q = p
+    while q > 1:
+        q = (q + 1) // 2
+        levels += 1
+    ov = (C.c_int32 * levels)()
+    ax = np.zeros(nx + 1)
+    ay = np.zeros(ny + 1)
+    dp = C.POINTER(C.c_double)
+    _raise(lib.sem_learned_params(pr.ctypes.data_as(C.POINTER(C.c_float)), nx, ny, p, bc, ov,
+                                  ax.ctypes.data_as(dp), ay.ctypes.data_as(dp)),
+           "sem_learned_params")
+    return list(ov), ax, ay
