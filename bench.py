@@ -15,7 +15,14 @@ Printed JSON line (one):
   cpu_baseline the CPU oracle on a bounded sample of the same workload
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload c2] [--n-o 1]
-                       [--precision fp64|mixed] [--no-cpu-baseline]
+                       [--precision fp64|mixed|bf16] [--weights paper|learned]
+                       [--no-cpu-baseline]
+
+With --precision mixed / bf16 or --weights learned the line also carries
+`plain_fp64_paper`: the plain method (FP64, the paper's parameters) timed on
+the same workload, and its speedup ratio.  --weights learned first runs the
+parameter sweeps and trains the network (outside the timed region; reported
+under `learned`).
 """
 from __future__ import annotations
 
@@ -35,12 +42,14 @@ FP64_PEAK_TFS = 78.6         # MI355X FP64 vector
 FP32_PEAK_TFS = 157.3        # MI355X FP32 vector
 RIDGE_FP64 = FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
 RIDGE_FP32 = FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+BF16_PEAK_TFS = 2500.0       # MI355X dense BF16 matrix cores
+RIDGE_BF16 = BF16_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fdm_traffic.json")
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fdm_impl.h", "kernels.h", "common.h"):
+    for f in ("fdm_impl.h", "fdm_mfma.hip", "kernels.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1512_02390_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -49,7 +58,10 @@ def kernel_source_hash() -> str:
 RULES = {"fixed": 0, "ceil8": 1, "floor8": 2, "ceil2": 3}
 
 
-def make_problem(name: str, n_o: int, precision: int, rule=None, overlaps=None):
+def make_problem(name: str, n_o: int, precision: int, rule=None, overlaps=None, net=None):
+    """Solver, right-hand side and initial guess of a workload; with a trained
+    network `net` the Schwarz parameters are the learned ones (the paper's
+    when the prediction is unusable)."""
     import numpy as np
     import torch
     from paper_1512_02390_amd import workloads as W
@@ -70,8 +82,15 @@ def make_problem(name: str, n_o: int, precision: int, rule=None, overlaps=None):
         xc, yc = probe.node_coords()
         probe.close()
         NU = W.nodal(nu.nu, xc, yc)
-    s = Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
-               precision=precision, overlaps=cfg.overlaps)
+    learned_params = None
+    if net is not None:
+        from paper_1512_02390_amd import learned as LW
+        s, learned_params = LW.solver_with_learned(cfg.xb, cfg.yb, cfg.p, cfg.bc, NU, net,
+                                                   precision)
+    else:
+        s = Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
+                   precision=precision, overlaps=cfg.overlaps)
+    s.learned_params = learned_params
     shape = s.shape()
     if name == "c1":
         xc, yc = s.node_coords()
@@ -142,10 +161,15 @@ def main():
                     help="overlap rule per level (default: the workload's)")
     ap.add_argument("--overlaps", default=None,
                     help="explicit overlaps of levels 1..L, comma separated")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "bf16"],
+                    help="fp64; mixed: FP32 V-cycle in FP64 MGCG; bf16: as mixed with the "
+                         "subdomain solves of wide tiles on BF16 matrix cores")
     ap.add_argument("--imax", type=int, default=200)
     ap.add_argument("--cycle", default=None, choices=["mg10", "mg11", "var11"],
                     help="smoothing schedule (default: mg10; mg11 for variable nu)")
+    ap.add_argument("--weights", default="paper", choices=["paper", "learned"],
+                    help="Schwarz parameters: the paper's, or predicted by a network trained "
+                         "on the solver's own sweeps before the timed region")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference "
@@ -158,7 +182,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1512_02390_amd.sem import FP64, MIXED_FP32
+    from paper_1512_02390_amd.sem import FP64, MIXED_BF16, MIXED_FP32
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -170,11 +194,27 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
         return
-    prec = FP64 if args.precision == "fp64" else MIXED_FP32
+    prec = {"fp64": FP64, "mixed": MIXED_FP32, "bf16": MIXED_BF16}[args.precision]
     ovl = None
     if args.overlaps:
         ovl = [0] + [int(v) for v in args.overlaps.split(",")]
-    cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec, args.rule, ovl)
+    net, learned_info = None, None
+    if args.weights == "learned":
+        from paper_1512_02390_amd import learned as LW
+        t0 = time.perf_counter()
+        X, T, recs = LW.make_dataset(LW.default_patches())
+        net, lh = LW.train(X, T)
+        learned_info = {"patches": len(recs), "samples": int(X.shape[0]),
+                        "candidates_per_patch": len(recs[0][1]),
+                        "train_loss": [lh[0], lh[-1]],
+                        "sweep_and_training_s": time.perf_counter() - t0}
+    cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec, args.rule, ovl, net)
+    if learned_info is not None:
+        learned_info["fallback_to_paper"] = s.learned_params is None
+        if s.learned_params is not None:
+            ax, ay = s.learned_params[1], s.learned_params[2]
+            learned_info["alpha_range"] = [float(min(ax.min(), ay.min())),
+                                           float(max(ax.max(), ay.max()))]
     cycle = args.cycle or ("mg11" if cfg.variable_nu else "mg10")
     L = s.L
     if cycle == "mg10":
@@ -191,6 +231,14 @@ def main():
     for _ in range(max(args.warmup, 1)):
         u = u0.clone()
         it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10, ns1, ns2)
+    if not ok and learned_info is not None and s.learned_params is not None:
+        # the learned parameters failed on this problem: the paper's take over
+        s.close()
+        cfg, s, b, u0, fn, NU = make_problem(args.workload, args.n_o, prec, args.rule, ovl)
+        learned_info["fallback_to_paper"] = "learned parameters did not converge"
+        for _ in range(max(args.warmup, 1)):
+            u = u0.clone()
+            it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10, ns1, ns2)
     if not ok:
         raise SystemExit(f"MGCG did not reach 1e-10 in {args.imax} iterations")
     r_bar = math.log10(hist[0] / hist[-1]) / it
@@ -222,12 +270,34 @@ def main():
     torch.cuda.synchronize()
     tv = (time.perf_counter() - tv0) / nv
 
+    # the plain method (FP64, the paper's parameters) on the same workload, for
+    # the mixed / learned comparison at equal accuracy
+    plain = None
+    if prec != FP64 or net is not None:
+        _, s0, b0, _, _, _ = make_problem(args.workload, args.n_o, FP64, args.rule, ovl)
+        for _ in range(max(args.warmup, 1)):
+            u = u0.clone()
+            it0, _, ok0 = s0.pcg_solve(u, b0, args.imax, 1e-10, ns1, ns2)
+        us0 = [u0.clone() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for k in range(args.steps):
+            s0.pcg_solve(us0[k], b0, args.imax, 1e-10, ns1, ns2)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - tp0) / args.steps
+        plain = {"time_to_1e-10_ms": 1e3 * tp if ok0 else None, "iterations": it0,
+                 "converged": bool(ok0),
+                 "overlap": [s0.level_info(l)[1] for l in range(1, s0.L + 1)],
+                 "speedup": (tp / (dt / args.steps)) if ok0 else None}
+        s0.close()
+
     flops, m = fdm_work(s, cfg)
     word = 8 if prec == FP64 else 4
     nbytes = 3.0 * rows * cols * word
     avg_ms = kms / max(nk, 1)
     ai = flops / nbytes
-    ridge = RIDGE_FP64 if prec == FP64 else RIDGE_FP32
+    mfma = prec == MIXED_BF16 and m >= 17
+    ridge = RIDGE_FP64 if prec == FP64 else (RIDGE_BF16 if mfma else RIDGE_FP32)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -246,7 +316,9 @@ def main():
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic
-    roof.update({"kernel": f"k_fdm<{'double' if prec == FP64 else 'float'},{m}>",
+    kname = (f"k_fdm_mfma<{(m + 15) // 16}> (m={m})" if mfma
+             else f"k_fdm<{'double' if prec == FP64 else 'float'},{m}>")
+    roof.update({"kernel": kname,
                  "avg_launch_ms": avg_ms, "launches": nk,
                  "algorithmic_flops": flops, "algorithmic_bytes": nbytes,
                  "achieved_tflops": flops / (avg_ms * 1e-3) / 1e12})
@@ -262,12 +334,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == FP64 else "f32+f64",
+        "dtype": {FP64: "f64", MIXED_FP32: "f32+f64", MIXED_BF16: "bf16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": cfg.description, "name": cfg.name, "elements": [cfg.nx, cfg.ny],
                    "p": cfg.p, "dof": n_dof, "solver": f"MGCG {cycle}, w_5",
                    "overlap": [s.level_info(l)[1] for l in range(1, s.L + 1)],
-                   "precision": args.precision, "rtol": 1e-10},
+                   "precision": args.precision, "weights": args.weights, "rtol": 1e-10},
         "time_to_1e-10_ms": 1e3 * dt / args.steps,
         "iterations": it,
         "r_bar": r_bar,
@@ -275,6 +347,10 @@ def main():
         "vcycle_dof_per_s": n_dof / tv,
         "roofline": roof,
     }
+    if plain is not None:
+        out["plain_fp64_paper"] = plain
+    if learned_info is not None:
+        out["learned"] = learned_info
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, fn, NU, ns1, ns2)
     print(json.dumps(out), flush=True)

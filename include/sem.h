@@ -59,9 +59,13 @@ typedef enum {
 } sem_overlap_rule;
 
 /* Arithmetic of the V-cycle used as preconditioner.  Vectors crossing the
- * ABI are always FP64.  SEM_MIXED_FP32 runs smoother, transfers and coarse
- * levels in FP32 inside an FP64 residual / CG outer iteration. */
-typedef enum { SEM_FP64 = 0, SEM_MIXED_FP32 = 1 } sem_precision;
+ * ABI are always FP64.  SEM_MIXED_FP32 runs smoother, residuals and
+ * transfers of the V-cycle in FP32 inside an FP64 residual / CG outer
+ * iteration (the coarse solve stays FP64).  SEM_MIXED_BF16 is SEM_MIXED_FP32
+ * with the subdomain solves of levels whose subdomain width
+ * p_l + 1 + 2 n_o is at least 17 on the matrix cores: BF16 operands, FP32
+ * accumulation. */
+typedef enum { SEM_FP64 = 0, SEM_MIXED_FP32 = 1, SEM_MIXED_BF16 = 2 } sem_precision;
 
 typedef struct {
   int32_t nx, ny;          /* elements per direction                      */

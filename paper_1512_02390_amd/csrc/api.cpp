@@ -11,6 +11,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sem.h"
@@ -78,7 +79,7 @@ struct Tables {
   T *Lhat = nullptr, *D = nullptr, *w = nullptr;
   T *sx = nullptr, *sy = nullptr, *mx = nullptr, *my = nullptr;
   T *Sx = nullptr, *SxT = nullptr, *SyW = nullptr, *SyT = nullptr, *dinv = nullptr;
-  T *wx = nullptr, *nuinv = nullptr, *nu = nullptr, *DT = nullptr;
+  T *wx = nullptr, *nuinv = nullptr, *nu = nullptr, *nuT = nullptr, *DT = nullptr;
   T *E = nullptr, *ET = nullptr;  // interpolation from level l-1 and its transpose
 };
 
@@ -314,7 +315,16 @@ void upload_tables(sem_ctx *h, Level &L, Tables<T> &t, const std::vector<double>
     t.wx = upload<T>(P, fx->wts);
   }
   if (!nuinv.empty()) t.nuinv = upload<T>(P, nuinv);
-  if (!L.nu_host.empty()) t.nu = upload<T>(P, L.nu_host);
+  if (!L.nu_host.empty()) {
+    t.nu = upload<T>(P, L.nu_host);
+    // transposed copy: the row-direction flux reads nu along rows with one
+    // lane per row, which is coalesced in this layout
+    const int R = L.g.rows, Cc = L.g.cols;
+    std::vector<double> nt((size_t)R * Cc);
+    for (int r = 0; r < R; ++r)
+      for (int c = 0; c < Cc; ++c) nt[(size_t)c * R + r] = L.nu_host[(size_t)r * Cc + c];
+    t.nuT = upload<T>(P, nt);
+  }
   if (!E.empty()) {
     t.E = upload<T>(P, E);
     const int nr = L.p + 1, nc = (int)(E.size() / nr);
@@ -492,7 +502,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   std::vector<double> nuinv;
   for (double v : nubar) nuinv.push_back(1.0 / v);
   if (!nuinv.empty()) h->enuinv = upload<double>(h->pool, nuinv);
-  const bool mixed = h->precision == SEM_MIXED_FP32;
+  const bool mixed = h->precision != SEM_FP64;
   // per-level tables
   for (int l = 0; l <= L; ++l) {
     Level &lv = h->lev[l];
@@ -673,7 +683,7 @@ template <typename T>
 void residual(sem_ctx *h, int l, const T *u, const T *f, T *out) {
   Level &L = h->lev[l];
   Tables<T> &t = tabs<T>(L);
-  ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu};
+  ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT};
   launch_residual<T>(a, h->stream);
 }
 
@@ -685,7 +695,14 @@ void fdm(sem_ctx *h, int l, const T *r, T *u) {
                t.wx, t.nuinv};
   const bool timed = (l == h->time_level) && h->ev_used + 2 <= h->ev.size();
   if (timed) HIP_OK(hipEventRecord(h->ev[h->ev_used], h->stream));
-  launch_fdm<T>(a, h->stream);
+  if constexpr (std::is_same<T, float>::value) {
+    if (h->precision == SEM_MIXED_BF16 && L.m >= kMfmaMinTile)
+      launch_fdm_bf16(a, h->stream);
+    else
+      launch_fdm<T>(a, h->stream);
+  } else {
+    launch_fdm<T>(a, h->stream);
+  }
   if (timed) {
     HIP_OK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
     h->ev_used += 2;
@@ -730,13 +747,17 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0) {
     launch_sub_mean(c.g, h->cf, h->scal + 8, s);
     f = h->cf;
   }
-  launch_fill<double>(u0, c.n(), 0.0, s);
   const int nx = h->cnx, ny = h->cny;
   const long ld = c.g.cols;
-  if (nx == 0 || ny == 0) return;  // no coarse unknowns (one Dirichlet element)
+  if (nx == 0 || ny == 0) {  // no coarse unknowns (one Dirichlet element)
+    launch_fill<double>(u0, c.n(), 0.0, s);
+    return;
+  }
   if (h->cMinv) {
+    launch_fill<double>(u0, c.n(), 0.0, s);
     launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
   } else {
+    launch_fill<double>(u0, c.n(), 0.0, s);
     // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T
     launch_gemm(ny, nx, ny, h->cSy, 1, ny, f + h->coff, ld, 1, h->cT1, nx, nullptr, 0, s);
     launch_gemm(ny, nx, nx, h->cT1, nx, 1, h->cSx, nx, 1, h->cT2, nx, h->cDinv, nx, s);
@@ -812,7 +833,7 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
 void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, const int32_t *ns2) {
   Level &top = h->lev.back();
   const long n = top.n();
-  if (h->precision == SEM_MIXED_FP32) {
+  if (h->precision != SEM_FP64) {
     launch_convert<double, float>(r, top.ff, n, 1.0, h->stream);
     launch_fill<float>(top.uf, n, 0.0f, h->stream);
     vcycle_impl<float>(h, top.uf, top.ff, ns1, ns2, true);
@@ -868,7 +889,7 @@ sem_status sem_setup(const sem_mesh *mesh, int32_t p, const sem_overlap *overlap
   auto *h = new (std::nothrow) sem_ctx();
   if (!h) return SEM_ENOMEM;
   h->stream = static_cast<hipStream_t>(stream);
-  if (precision != SEM_FP64 && precision != SEM_MIXED_FP32) {
+  if (precision != SEM_FP64 && precision != SEM_MIXED_FP32 && precision != SEM_MIXED_BF16) {
     g_setup_err = "unknown precision";
     delete h;
     return SEM_EINVAL;
@@ -959,7 +980,7 @@ sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *n
   return guard(h, [&] {
     Level &top = h->lev.back();
     launch_zero_boundary<double>(top.g, u, h->stream);
-    if (h->precision == SEM_MIXED_FP32) {
+    if (h->precision != SEM_FP64) {
       // MG(u, f) = u + MG(0, f - A u): residual in FP64, cycle in FP32
       residual<double>(h, (int)h->lev.size() - 1, u, f, h->pr);
       precondition(h, h->pr, h->pz, ns1, ns2);

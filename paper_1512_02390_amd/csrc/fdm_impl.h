@@ -48,12 +48,20 @@ __device__ __forceinline__ T urow_dot(const T *__restrict__ row, const T (&x)[M]
   return a0 + a1;
 }
 
+// Output rows per loop iteration: two for small tiles, so that the scalar
+// loads of the next factor row overlap the current row's FMAs; one row (the
+// largest set of factor values held in scalar registers) beyond that.
+template <typename T, int M>
+constexpr int fdm_rows_per_iter() { return M * (int)sizeof(T) <= 128 ? 2 : 1; }
+
 template <typename T, int M>
 __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
+  constexpr int RU = fdm_rows_per_iter<T, M>();
   constexpr int EPW = 64 / M;
   constexpr int LS = M + 1;  // LDS row stride
-  // one tile per element plus a scratch tile for the idle lanes of the wave
-  __shared__ T lds[(EPW + 1) * M * LS];
+  // one tile per element slot; lanes beyond the last slot read slot EPW-1
+  // and never write
+  __shared__ T lds[EPW * M * LS];
   const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
   const int ty = task->ty, tx = task->tx, cnt = task->count;
   const int lane = threadIdx.x;
@@ -79,7 +87,7 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   } else {
     vc = gc >= 1 && gc <= g.cols - 2;
   }
-  T *tile = lds + (has_tile ? k : EPW) * M * LS;
+  T *tile = lds + (has_tile ? k : EPW - 1) * M * LS;
 
   // ---- gather the residual tile column (branch-free, always in bounds) ----
   T X[M];
@@ -99,38 +107,51 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     X[i] = ok ? v : T(0);
   }
   // ---- stage 1: T1 = S_y^T R, lane = column j; row a of T1 -> LDS ----------
-#pragma unroll 1
+#pragma unroll RU
   for (int a = 0; a < M; ++a) {
-    tile[a * LS + j] = urow_dot<T, M>(SyT + a * M, X);
+    const T v = urow_dot<T, M>(SyT + a * M, X);
+    if (has_tile) tile[a * LS + j] = v;
   }
   __syncthreads();
-  // ---- stage 2: T2 = T1 S_x, lane = row j --------------------------------------
+  // ---- stage 2: T2 = T1 S_x, lane = row j, divided by nu_bar (lambda_y + lambda_x)
 #pragma unroll
   for (int b = 0; b < M; ++b) X[b] = tile[j * LS + b];
-  T dv[M];
-  {
-    const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
-    const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
+  const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
+  const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
+  if constexpr (M <= 32) {
+    // the row of 1/(lambda_y + lambda_x) fits in registers next to the tile row
+    T dv[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) dv[c] = d[c] * s;
-  }
-#pragma unroll 1
-  for (int c = 0; c < M; ++c) {
-    tile[j * LS + c] = urow_dot<T, M>(SxT + c * M, X);
-  }
-  // divide by nu_bar (lambda_y + lambda_x), then stage 3: T3 = T2 S_x^T
+#pragma unroll RU
+    for (int c = 0; c < M; ++c) {
+      const T v = urow_dot<T, M>(SxT + c * M, X);
+      if (has_tile) tile[j * LS + c] = v;
+    }
 #pragma unroll
-  for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c] * dv[c];
+    for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c] * dv[c];
+  } else {
+    // large tiles: scale each output as it is produced
 #pragma unroll 1
+    for (int c = 0; c < M; ++c) {
+      const T v = urow_dot<T, M>(SxT + c * M, X) * (d[c] * s);
+      if (has_tile) tile[j * LS + c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c];
+  }
+  // ---- stage 3: T3 = T2 S_x^T ------------------------------------------------------
+#pragma unroll RU
   for (int b = 0; b < M; ++b) {
-    tile[j * LS + b] = urow_dot<T, M>(Sx + b * M, X);
+    const T v = urow_dot<T, M>(Sx + b * M, X);
+    if (has_tile) tile[j * LS + b] = v;
   }
   __syncthreads();
   // ---- stage 4: du = diag(w_y) S_y T3, lane = column j; weighted scatter-add ------
 #pragma unroll
   for (int a = 0; a < M; ++a) X[a] = tile[a * LS + j];
   const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
-#pragma unroll 1
+#pragma unroll RU
   for (int i = 0; i < M; ++i) {
     const T v = urow_dot<T, M>(SyW + i * M, X);
     int gr = row0 + i;

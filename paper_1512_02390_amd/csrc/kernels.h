@@ -36,6 +36,7 @@ struct ResidualArgs {
   const T *sx, *sy;      // per element 2/h (x: nx, y: ny)
   const T *mx, *my;      // per element h/2
   const T *nu;           // nodal diffusivity (node array) or null
+  const T *nuT;          // the same, transposed (cols x rows), or null
 };
 
 template <typename T>
@@ -55,6 +56,10 @@ struct FdmArgs {
 
 template <typename T>
 void launch_residual(const ResidualArgs<T> &a, hipStream_t s);
+// FP32 tables and vectors, BF16 matrix-core products with FP32 accumulation
+// (m <= 48); used for tiles of at least kMfmaMinTile nodes.
+constexpr int kMfmaMinTile = 17;
+void launch_fdm_bf16(const FdmArgs<float> &a, hipStream_t s);
 template <typename T>
 void launch_fdm(const FdmArgs<T> &a, hipStream_t s);
 

@@ -10,15 +10,17 @@
 // receives the contribution of the neighbouring element, recomputed here so
 // that no two wavefronts write the same node (no atomics, deterministic).
 //
-//  y-part: lane = node column; the column's 2p+1 values of the element row and
-//          the one below are held in registers and contracted with the
-//          wave-uniform 1-D operator (scalar-register operands).
-//  x-part: the p owned rows are staged in LDS with a halo of p columns on the
-//          left and one on the right; lane = (row, element) contracts its row
-//          segment, writes the result back to LDS, and the column lanes pick
-//          it up.
-// The two directions are combined with the assembled diagonal mass:
-//   (A u)(row, col) = M_y(row) xpart + M_x(col) ypart.
+//  1. lane = node column: the column's p+1 values of the element row stay in
+//     registers; the p owned rows are staged in LDS with a halo of p columns
+//     on the left and one on the right; the element below's contribution to
+//     the shared bottom node is contracted right away.
+//  2. x-part, lane = (row, element): contracts its row segment with the
+//     wave-uniform 1-D operator (scalar-register operands) and writes the p
+//     results to LDS (over the staged rows for p <= 16).
+//  3. y-part, lane = node column: one output row per iteration, combined at
+//     once with the x-part and the assembled diagonal mass,
+//       (A u)(row, col) = M_y(row) xpart + M_x(col) ypart,
+//     and stored; the y-part never goes through LDS.
 
 #include "common.h"
 #include "kernels.h"
@@ -43,10 +45,15 @@ __device__ __forceinline__ T udot(const T *__restrict__ row, const T (&x)[N]) {
 // out[o * ostride] = s * (Op row o) . x  for o < nout, where Op is a
 // wave-uniform (P+1)-column table.  The loop is kept rolled: each iteration
 // brings one table row into scalar registers.
+// Rows per iteration: two when a table row is at most 128 bytes (the next
+// row's scalar loads then overlap the current row's FMAs), else one.
+template <typename T, int P>
+constexpr int rows_per_iter() { return (P + 1) * (int)sizeof(T) <= 128 ? 2 : 1; }
+
 template <typename T, int P>
 __device__ __forceinline__ void rows_apply(const T *__restrict__ Op, const T (&x)[P + 1], T s,
                                            T *out, int ostride, int nout) {
-#pragma unroll 1
+#pragma unroll rows_per_iter<T, P>()
   for (int o = 0; o < nout; ++o) out[o * ostride] = s * udot<T, P + 1>(Op + o * (P + 1), x);
 }
 
@@ -98,9 +105,12 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
   constexpr int LW = W + P + 1;
-  __shared__ T su[P][LW];                      // owned rows, halo p left, 1 right
-  __shared__ T sxp[P][W];                      // x-part per owned node
-  __shared__ T syp[P][W];                      // y-part per owned node
+  // For P <= 16 the x-part results overwrite the staged rows (one LDS array);
+  // larger orders keep them apart so that the left segment can be read after
+  // the main contraction without holding it in registers.
+  constexpr bool kAlias = P <= 16;
+  __shared__ T su[P][LW];                         // owned rows, halo p left, 1 right
+  __shared__ T sxp_own[kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
   __shared__ T spv[NU ? 64 : 1][NU ? P + 2 : 1];  // private flux slots (variable nu)
   const Grid g = A.g;
   const int per = g.periodic;
@@ -112,46 +122,23 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   const int eym = per ? wrap(ey - 1, g.ny) : ey - 1;
   const bool has_below = per || ey > 0;
   T *pv = NU ? &spv[lane][0] : nullptr;
+  auto sxp = [&](int a, int c) -> T & {
+    if constexpr (kAlias) return su[a][c];
+    else return sxp_own[a][c];
+  };
 
-  // ---- y-part (lane = column) ----------------------------------------------
+  // ---- column of the element row (lane = column) ---------------------------
   const int c = lane;
   const int gc = c0 + c;
   // last column needed by this strip: the right end of its last element
   const int last_col = min(c0 + W, g.nx * P);
   const bool col_lane = c < W && gc <= last_col;
   const int gcs = col_lane ? gc : 0;  // a safe column for idle lanes
-  T *ycol = &syp[0][col_lane ? c : 0];
-  {
-    T seg[P + 1];
-    load_col<T, P>(A.u, r0, gc, g, col_lane, seg);
-    // stage the owned rows for the x-part
-    if (col_lane) {
+  T yv[P + 1];     // y-direction input: the u segment, or its flux for variable nu
+  load_col<T, P>(A.u, r0, gc, g, col_lane, yv);
+  if (col_lane) {
 #pragma unroll
-      for (int a = 0; a < P; ++a) su[a][P + c] = seg[a];
-    }
-    if constexpr (NU) {
-      T v[P + 1];
-      nu_flux<T, P>(A.D, A.w, seg,
-                    [&](int b) { return coef_value(A.nu, r0 + b, gcs, g.rows, g.cols, per); }, pv, v);
-      if (col_lane) rows_apply<T, P>(A.DT, v, A.sy[ey], ycol, W, P);
-    } else {
-      if (col_lane) rows_apply<T, P>(A.Lhat, seg, A.sy[ey], ycol, W, P);
-    }
-  }
-  if (has_below) {
-    // the element below contributes to the shared bottom row (local node P)
-    T seg[P + 1];
-    load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
-    T extra;
-    if constexpr (NU) {
-      T v[P + 1];
-      nu_flux<T, P>(A.D, A.w, seg,
-                    [&](int b) { return coef_value(A.nu, r0 - P + b, gcs, g.rows, g.cols, per); }, pv, v);
-      extra = last_row<T, P>(A.DT, v, A.sy[eym], pv);
-    } else {
-      extra = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
-    }
-    if (col_lane) ycol[0] += extra;
+    for (int a = 0; a < P; ++a) su[a][P + c] = yv[a];
   }
   // halo columns of the owned rows
   if (lane < P || (lane == P && c0 + W <= last_col)) {
@@ -160,60 +147,101 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
 #pragma unroll
     for (int a = 0; a < P; ++a) su[a][k] = node_value(A.u, r0 + a, col, g.rows, g.cols, per);
   }
+  // the element below contributes to the shared bottom row (local node P)
+  T extra_y = T(0);
+  if (has_below) {
+    T seg[P + 1];
+    load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
+    if constexpr (NU) {
+      T v[P + 1];
+      nu_flux<T, P>(A.D, A.w, seg,
+                    [&](int b) { return coef_value(A.nu, r0 - P + b, gcs, g.rows, g.cols, per); }, pv, v);
+      extra_y = last_row<T, P>(A.DT, v, A.sy[eym], pv);
+    } else {
+      extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
+    }
+  }
+  if constexpr (NU) {
+    T v[P + 1];
+    nu_flux<T, P>(A.D, A.w, yv,
+                  [&](int b) { return coef_value(A.nu, r0 + b, gcs, g.rows, g.cols, per); }, pv, v);
+#pragma unroll
+    for (int b = 0; b <= P; ++b) yv[b] = v[b];
+  }
   __syncthreads();
 
   // ---- x-part (lane = (row a, element q)) -------------------------------------
   {
     const int q = lane / P, a = lane - (lane / P) * P;
     const int ex = e0 + q;
-    if (lane < W && ex < g.nx) {
-      T *xrow = &sxp[a][q * P];
-      T seg[P + 1];
+    const bool xlane = lane < W && ex < g.nx;
+    const bool has_left = per || ex > 0;
+    const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
+    T seg[P + 1], segl[kAlias ? P + 1 : 1];
+    if (xlane) {
 #pragma unroll
       for (int b = 0; b <= P; ++b) seg[b] = su[a][P + q * P + b];
+      if constexpr (kAlias) {
+#pragma unroll
+        for (int b = 0; b <= P; ++b) segl[b] = su[a][q * P + b];
+      }
+    }
+    if constexpr (kAlias) __syncthreads();   // the results overwrite su below
+    if (xlane) {
+      T *xrow = &sxp(a, q * P);
       if constexpr (NU) {
         T v[P + 1];
         nu_flux<T, P>(A.D, A.w, seg,
-                      [&](int b) { return coef_value(A.nu, r0 + a, c0 + q * P + b, g.rows, g.cols, per); },
+                      [&](int b) { return coef_value(A.nuT, c0 + q * P + b, r0 + a, g.cols, g.rows, per); },
                       pv, v);
         rows_apply<T, P>(A.DT, v, A.sx[ex], xrow, 1, P);
       } else {
         rows_apply<T, P>(A.Lhat, seg, A.sx[ex], xrow, 1, P);
       }
-      if (per || ex > 0) {
-        const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
-#pragma unroll
-        for (int b = 0; b <= P; ++b) seg[b] = su[a][q * P + b];
-        T extra;
-        if constexpr (NU) {
-          T v[P + 1];
-          nu_flux<T, P>(A.D, A.w, seg,
-                        [&](int b) {
-                          return coef_value(A.nu, r0 + a, c0 + q * P - P + b, g.rows, g.cols, per);
-                        },
-                        pv, v);
-          extra = last_row<T, P>(A.DT, v, A.sx[exm], pv);
+      if (has_left) {
+        // contribution of the left neighbour to the shared left node
+        auto extra_of = [&](const T(&sl)[P + 1]) -> T {
+          if constexpr (NU) {
+            T v[P + 1];
+            nu_flux<T, P>(A.D, A.w, sl,
+                          [&](int b) {
+                            return coef_value(A.nuT, c0 + q * P - P + b, r0 + a, g.cols, g.rows, per);
+                          },
+                          pv, v);
+            return last_row<T, P>(A.DT, v, A.sx[exm], pv);
+          } else {
+            return A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), sl);
+          }
+        };
+        if constexpr (kAlias) {
+          xrow[0] += extra_of(segl);
         } else {
-          extra = A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
+#pragma unroll
+          for (int b = 0; b <= P; ++b) seg[b] = su[a][q * P + b];
+          xrow[0] += extra_of(seg);
         }
-        xrow[0] += extra;
       }
     }
   }
   __syncthreads();
 
-  // ---- combine with the assembled mass and store -------------------------------------
+  // ---- y-part combined with the x-part and the assembled mass (lane = column) ----
+  //   (A u)(row, col) = M_y(row) xpart + M_x(col) ypart
   const int q = c / P, al = c - (c / P) * P;
   const int ex = e0 + q;
   if (col_lane && ex < g.nx) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-#pragma unroll
+    const T *__restrict__ Op = NU ? A.DT : A.Lhat;
+    const T sy = A.sy[ey];
+#pragma unroll rows_per_iter<T, P>()
     for (int a = 0; a < P; ++a) {
+      T yp = sy * udot<T, P + 1>(Op + a * (P + 1), yv);
+      if (a == 0) yp += extra_y;
       const int row = r0 + a;
       const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
-      const T au = myr * sxp[a][c] + mxc * syp[a][c];
+      const T au = myr * sxp(a, c) + mxc * yp;
       T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
@@ -226,7 +254,6 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
   }
 }
-
 }  // namespace
 
 template <typename T, int P>
