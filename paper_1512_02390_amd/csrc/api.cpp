@@ -126,7 +126,7 @@ struct sem_ctx {
   double *pr = nullptr, *pp = nullptr, *pq = nullptr, *pz = nullptr, *pro = nullptr;
   double *partial = nullptr, *scal = nullptr;  // scal: device scalars
   // element widths and 1/nu_bar per element (element features)
-  double *hx = nullptr, *hy = nullptr, *enuinv = nullptr;
+  double *hx = nullptr, *hy = nullptr, *enuinv = nullptr, *enu = nullptr;  // enu: finest nodal nu
   // optional event timing of the Schwarz kernel on one level
   int time_level = -1;
   std::vector<hipEvent_t> ev;
@@ -316,14 +316,20 @@ void upload_tables(sem_ctx *h, Level &L, Tables<T> &t, const std::vector<double>
   }
   if (!nuinv.empty()) t.nuinv = upload<T>(P, nuinv);
   if (!L.nu_host.empty()) {
-    t.nu = upload<T>(P, L.nu_host);
-    // transposed copy: the row-direction flux reads nu along rows with one
-    // lane per row, which is coalesced in this layout
-    const int R = L.g.rows, Cc = L.g.cols;
-    std::vector<double> nt((size_t)R * Cc);
+    // nu times the GLL weight of the contraction direction (a node on an
+    // element interface has local index 0 or p, whose weights are equal);
+    // the row-direction table is transposed: that flux reads nu along rows
+    // with one lane per row, which is coalesced in this layout
+    const int R = L.g.rows, Cc = L.g.cols, pp = L.p;
+    std::vector<double> ny_((size_t)R * Cc), nx_((size_t)R * Cc);
     for (int r = 0; r < R; ++r)
-      for (int c = 0; c < Cc; ++c) nt[(size_t)c * R + r] = L.nu_host[(size_t)r * Cc + c];
-    t.nuT = upload<T>(P, nt);
+      for (int c = 0; c < Cc; ++c) {
+        const double v = L.nu_host[(size_t)r * Cc + c];
+        ny_[(size_t)r * Cc + c] = v * w[r % pp];
+        nx_[(size_t)c * R + r] = v * w[c % pp];
+      }
+    t.nu = upload<T>(P, ny_);
+    t.nuT = upload<T>(P, nx_);
   }
   if (!E.empty()) {
     t.E = upload<T>(P, E);
@@ -502,6 +508,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   std::vector<double> nuinv;
   for (double v : nubar) nuinv.push_back(1.0 / v);
   if (!nuinv.empty()) h->enuinv = upload<double>(h->pool, nuinv);
+  if (nu) h->enu = upload<double>(h->pool, h->lev.back().nu_host);
   const bool mixed = h->precision != SEM_FP64;
   // per-level tables
   for (int l = 0; l <= L; ++l) {
@@ -1083,7 +1090,7 @@ sem_status sem_elem_features(sem_handle h, float *feat) {
   if (!h || !feat) return SEM_EINVAL;
   return guard(h, [&] {
     Level &top = h->lev.back();
-    launch_features(top.g, h->varnu ? top.td.nu : nullptr, h->enuinv, h->hx, h->hy, feat,
+    launch_features(top.g, h->enu, h->enuinv, h->hx, h->hy, feat,
                     h->stream);
   });
 }

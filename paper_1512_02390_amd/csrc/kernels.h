@@ -35,8 +35,11 @@ struct ResidualArgs {
   const T *w;            // p+1 GLL weights
   const T *sx, *sy;      // per element 2/h (x: nx, y: ny)
   const T *mx, *my;      // per element h/2
-  const T *nu;           // nodal diffusivity (node array) or null
-  const T *nuT;          // the same, transposed (cols x rows), or null
+  // variable diffusivity (null for the Poisson operator), with the GLL weight
+  // of the contraction direction folded in: nu(row, col) w_(row mod p) as a
+  // node array, and nu(row, col) w_(col mod p) transposed (cols x rows)
+  const T *nu;
+  const T *nuT;
 };
 
 template <typename T>

@@ -58,15 +58,16 @@ __device__ __forceinline__ void rows_apply(const T *__restrict__ Op, const T (&x
 }
 
 // Variable-coefficient flux of one element segment: v[a] = w_a nu_a (D seg)[a],
-// computed through the lane's private LDS slot pv; nu_at(a) gives nu at local
-// node a (read on the fly to keep register pressure low).
+// computed through the lane's private LDS slot pv; nuw_at(a) gives the
+// product w_a nu_a at local node a (a nodal table with the GLL weight of the
+// contraction direction folded in, read on the fly to keep register pressure
+// low).
 template <typename T, int P, typename NuAt>
-__device__ __forceinline__ void nu_flux(const T *__restrict__ D, const T *__restrict__ w,
-                                        const T (&seg)[P + 1], NuAt nu_at, T *pv, T (&v)[P + 1]) {
+__device__ __forceinline__ void nu_flux(const T *__restrict__ D, const T (&seg)[P + 1],
+                                        NuAt nuw_at, T *pv, T (&v)[P + 1]) {
   rows_apply<T, P>(D, seg, T(1), pv, 1, P + 1);
-  const T *__restrict__ wq = opaque(w);
 #pragma unroll
-  for (int a = 0; a <= P; ++a) v[a] = pv[a] * (wq[a] * nu_at(a));
+  for (int a = 0; a <= P; ++a) v[a] = pv[a] * nuw_at(a);
 }
 
 // s * (row P of a uniform table) . x through the rolled loop (one row).
@@ -112,6 +113,20 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   __shared__ T su[P][LW];                         // owned rows, halo p left, 1 right
   __shared__ T sxp_own[kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
   __shared__ T spv[NU ? 64 : 1][NU ? P + 2 : 1];  // private flux slots (variable nu)
+  // Variable nu with long rows: D and D^T are read from LDS (broadcast reads)
+  // instead of through the scalar cache, which the two tables overflow.
+  constexpr bool kOpLds = NU && P >= 16;
+  __shared__ T sop[kOpLds ? 2 * (P + 1) * (P + 1) : 1];
+  const T *Dm = A.D, *DTm = A.DT;
+  if constexpr (kOpLds) {
+    for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += 64) {
+      sop[i] = A.D[i];
+      sop[(P + 1) * (P + 1) + i] = A.DT[i];
+    }
+    Dm = sop;
+    DTm = sop + (P + 1) * (P + 1);
+    __syncthreads();
+  }
   const Grid g = A.g;
   const int per = g.periodic;
   const int lane = threadIdx.x;
@@ -121,7 +136,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   const int r0 = ey * P;
   const int eym = per ? wrap(ey - 1, g.ny) : ey - 1;
   const bool has_below = per || ey > 0;
-  T *pv = NU ? &spv[lane][0] : nullptr;
+  T *pv = &spv[NU ? lane : 0][0];   // always an LDS address (ds_ instructions)
   auto sxp = [&](int a, int c) -> T & {
     if constexpr (kAlias) return su[a][c];
     else return sxp_own[a][c];
@@ -154,16 +169,16 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
     if constexpr (NU) {
       T v[P + 1];
-      nu_flux<T, P>(A.D, A.w, seg,
+      nu_flux<T, P>(Dm, seg,
                     [&](int b) { return coef_value(A.nu, r0 - P + b, gcs, g.rows, g.cols, per); }, pv, v);
-      extra_y = last_row<T, P>(A.DT, v, A.sy[eym], pv);
+      extra_y = last_row<T, P>(DTm, v, A.sy[eym], pv);
     } else {
       extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
     }
   }
   if constexpr (NU) {
     T v[P + 1];
-    nu_flux<T, P>(A.D, A.w, yv,
+    nu_flux<T, P>(Dm, yv,
                   [&](int b) { return coef_value(A.nu, r0 + b, gcs, g.rows, g.cols, per); }, pv, v);
 #pragma unroll
     for (int b = 0; b <= P; ++b) yv[b] = v[b];
@@ -191,10 +206,10 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
       T *xrow = &sxp(a, q * P);
       if constexpr (NU) {
         T v[P + 1];
-        nu_flux<T, P>(A.D, A.w, seg,
+        nu_flux<T, P>(Dm, seg,
                       [&](int b) { return coef_value(A.nuT, c0 + q * P + b, r0 + a, g.cols, g.rows, per); },
                       pv, v);
-        rows_apply<T, P>(A.DT, v, A.sx[ex], xrow, 1, P);
+        rows_apply<T, P>(DTm, v, A.sx[ex], xrow, 1, P);
       } else {
         rows_apply<T, P>(A.Lhat, seg, A.sx[ex], xrow, 1, P);
       }
@@ -203,12 +218,12 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
         auto extra_of = [&](const T(&sl)[P + 1]) -> T {
           if constexpr (NU) {
             T v[P + 1];
-            nu_flux<T, P>(A.D, A.w, sl,
+            nu_flux<T, P>(Dm, sl,
                           [&](int b) {
                             return coef_value(A.nuT, c0 + q * P - P + b, r0 + a, g.cols, g.rows, per);
                           },
                           pv, v);
-            return last_row<T, P>(A.DT, v, A.sx[exm], pv);
+            return last_row<T, P>(DTm, v, A.sx[exm], pv);
           } else {
             return A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), sl);
           }
@@ -233,7 +248,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const T *__restrict__ Op = NU ? A.DT : A.Lhat;
+    const T *__restrict__ Op = NU ? DTm : A.Lhat;
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
     for (int a = 0; a < P; ++a) {
