@@ -147,8 +147,11 @@ sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *n
                       const int32_t *ns2);
 
 /* Inexact multigrid-preconditioned CG (Algorithm 4) until
- * ||r||_2 <= rtol ||r_0||_2 or imax iterations.  Synchronises the stream
- * once per iteration for the stopping test.  iters: iterations done;
+ * ||r||_2 <= rtol ||r_0||_2 or imax iterations.  The host waits once per
+ * iteration for ||r|| (the stopping test) while the next iteration's
+ * preconditioner is already queued; on return u holds the solution, and work
+ * queued after the final test (which touches only internal vectors) may
+ * still be running on the stream.  iters: iterations done;
  * res_hist: optional host array of imax+1 residual norms.  Returns
  * SEM_ENOCONV when imax is reached (u holds the last iterate). */
 sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax, double rtol,

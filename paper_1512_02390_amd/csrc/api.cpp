@@ -132,8 +132,14 @@ struct sem_ctx {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   std::string err;
+  // pinned host slots and events for reading residual norms asynchronously
+  double *pin = nullptr;
+  hipEvent_t nev[2] = {nullptr, nullptr};
   ~sem_ctx() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : nev)
+      if (e) (void)hipEventDestroy(e);
+    if (pin) (void)hipHostFree(pin);
   }
 };
 
@@ -672,6 +678,9 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     h->pro = dalloc<double>(h->pool, n);
     h->partial = dalloc<double>(h->pool, 2 * kRedBlocks);
     h->scal = dalloc<double>(h->pool, 16);
+    HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&h->pin), 2 * sizeof(double),
+                         hipHostMallocDefault));
+    for (hipEvent_t &e : h->nev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   HIP_OK(hipDeviceSynchronize());
 }
@@ -1028,23 +1037,53 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     if (res_hist) res_hist[0] = r0;
     precondition(h, r, p, ns1, ns2);
     launch_dot(p, r, n, h->partial, sc + 0, st);
-    int it = 0;
-    bool done = r0 == 0.0;
-    for (it = 1; it <= imax && !done; ++it) {
+    // The stopping test of iteration k needs ||r_k|| on the host.  Its copy
+    // into pinned memory is queued behind the update, and, unless the
+    // residual history predicts that this test will pass, the next
+    // iteration's preconditioner, direction and A p (which write only z, p,
+    // r_old, q and scalars, never u or r) are queued before the host waits
+    // for it, so the device does not idle during the round trip.  When the
+    // test passes, queued work is discarded; u and r are final.
+    auto q_and_pq = [&] {
       residual<double>(h, L, p, nullptr, q);             // q = A p
       launch_dot(p, q, n, h->partial, sc + 1, st);       // p.q
+    };
+    auto next_direction = [&] {
+      precondition(h, r, z, ns1, ns2);
+      launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
+      launch_cg_direction(sc + 6, sc + 0, p, z, ro, r, n, st);  // beta = z.(r-r_old)/delta
+      launch_copy_scalar(sc + 7, sc + 0, st);            // delta = z.r
+    };
+    int it = 0;
+    bool done = r0 == 0.0;
+    double prev1 = r0, prev2 = 0.0;   // the last two residual norms
+    if (!done && imax > 0) q_and_pq();
+    for (it = 1; it <= imax && !done; ++it) {
       launch_cg_update(sc, u, p, r, q, n, h->partial, sc + 2, st);  // alpha = delta / p.q
-      const double rn = std::sqrt(read_scalar(h, sc + 2));
+      double *slot = h->pin + (it & 1);
+      HIP_OK(hipMemcpyAsync(slot, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipEventRecord(h->nev[it & 1], st));
+      // predicted ||r_k|| from the last two reductions
+      const double pred = prev2 > 0.0 ? prev1 * (prev1 / prev2) : prev1;
+      const bool ahead = it < imax && !(pred <= 4.0 * rtol * r0);
+      if (ahead) {
+        next_direction();
+        q_and_pq();
+      }
+      HIP_OK(hipEventSynchronize(h->nev[it & 1]));
+      const double rn = std::sqrt(*slot);
       if (res_hist) res_hist[it] = rn;
       if (!std::isfinite(rn)) throw Fail{SEM_ENAN, "non-finite residual"};
       if (rn <= rtol * r0) {
         done = true;
         break;
       }
-      precondition(h, r, z, ns1, ns2);
-      launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
-      launch_cg_direction(sc + 6, sc + 0, p, z, ro, r, n, st);  // beta = z.(r-r_old)/delta
-      launch_copy_scalar(sc + 7, sc + 0, st);            // delta = z.r
+      if (!ahead && it < imax) {
+        next_direction();
+        q_and_pq();
+      }
+      prev2 = prev1;
+      prev1 = rn;
     }
     if (iters) *iters = done ? std::min(it, imax) : imax;
     if (!done) conv = SEM_ENOCONV;
