@@ -241,7 +241,10 @@ def main():
             it, hist, ok = s.pcg_solve(u, b, args.imax, 1e-10, ns1, ns2)
     if not ok:
         raise SystemExit(f"MGCG did not reach 1e-10 in {args.imax} iterations")
-    r_bar = math.log10(hist[0] / hist[-1]) / it
+    from paper_1512_02390_amd import metrics as MT
+    r_bar = MT.rbar(hist)
+    ov_levels = [0] + [s.level_info(l)[1] for l in range(1, s.L + 1)]
+    w_iter = MT.cycle_cost(cfg.p, ov_levels, [a + c for a, c in zip(ns1, ns2)])
 
     # one private copy of the initial guess per timed step: no copies inside
     us = [u0.clone() for _ in range(args.steps)]
@@ -343,6 +346,9 @@ def main():
         "time_to_1e-10_ms": 1e3 * dt / args.steps,
         "iterations": it,
         "r_bar": r_bar,
+        "n10": MT.n10(r_bar),
+        "omega": w_iter / r_bar,
+        "omega_tables": w_iter / r_bar * (cfg.p + 1) / cfg.p,
         "vcycle_ms": 1e3 * tv,
         "vcycle_dof_per_s": n_dof / tv,
         "roofline": roof,

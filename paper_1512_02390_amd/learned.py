@@ -26,6 +26,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import workloads as W
+from .metrics import cycle_cost, level_orders, rbar  # noqa: F401  (re-exported)
 from .sem import MLP, SemError, Solver, learned_params
 
 ALPHAS = (0.25, 0.5, 0.75, 1.0)
@@ -38,39 +39,11 @@ SWEEP_ITERS = 6
 SEED_SWEEP = 100
 
 
-def level_orders(p: int):
-    ps = [p]
-    while ps[-1] > 1:
-        ps.append((ps[-1] + 1) // 2)
-    return ps[::-1]
-
-
 def overlaps_for(rho: float, p: int):
     """n_o per level for overlap ratio rho (the library's rule)."""
     ov, _, _ = learned_params(np.array([[1.0, 2.0 * rho]], dtype=np.float32), 1, 1, p,
                               W.BC_DIRICHLET)
     return ov
-
-
-def cycle_cost(p: int, overlaps, ns, c_cg: float = 2.0) -> float:
-    """Work of one MGCG iteration in units of one finest-level operator
-    application: sum over smoothed levels of the relative level size times
-    (2 (m_l / n_p,l)^3 smoothing steps + 1 residual), plus c_CG / 2 (the
-    generalisation of the paper's omega cost to one overlap per level)."""
-    orders = level_orders(p)
-    w = c_cg / 2.0
-    for l in range(1, len(orders)):
-        pl = orders[l]
-        m = pl + 1 + 2 * overlaps[l]
-        w += (pl / p) ** 2 * (2.0 * (m / (pl + 1)) ** 3 * ns[l] + 1.0)
-    return w
-
-
-def rbar(hist) -> float:
-    n = len(hist) - 1
-    if n < 1 or not (hist[-1] > 0) or not np.all(np.isfinite(hist)):
-        return 0.0
-    return math.log10(hist[0] / hist[-1]) / n
 
 
 @dataclass
