@@ -80,6 +80,7 @@ struct Tables {
   T *sx = nullptr, *sy = nullptr, *mx = nullptr, *my = nullptr;
   T *Sx = nullptr, *SxT = nullptr, *SyW = nullptr, *SyT = nullptr, *dinv = nullptr;
   T *wx = nullptr, *nuinv = nullptr, *nu = nullptr, *nuT = nullptr, *DT = nullptr;
+  T *gy = nullptr, *gx = nullptr;  // flux scratch of the variable-nu residual
   T *E = nullptr, *ET = nullptr;  // interpolation from level l-1 and its transpose
 };
 
@@ -336,6 +337,8 @@ void upload_tables(sem_ctx *h, Level &L, Tables<T> &t, const std::vector<double>
       }
     t.nu = upload<T>(P, ny_);
     t.nuT = upload<T>(P, nx_);
+    t.gy = dalloc<T>(P, (size_t)L.g.ny * (pp + 1) * Cc);
+    t.gx = dalloc<T>(P, (size_t)L.g.nx * (pp + 1) * R);
   }
   if (!E.empty()) {
     t.E = upload<T>(P, E);
@@ -699,7 +702,8 @@ template <typename T>
 void residual(sem_ctx *h, int l, const T *u, const T *f, T *out) {
   Level &L = h->lev[l];
   Tables<T> &t = tabs<T>(L);
-  ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT};
+  ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT,
+                    t.gy, t.gx};
   launch_residual<T>(a, h->stream);
 }
 

@@ -40,6 +40,9 @@ struct ResidualArgs {
   // node array, and nu(row, col) w_(col mod p) transposed (cols x rows)
   const T *nu;
   const T *nuT;
+  // flux scratch of the variable-nu residual (owned by the level):
+  // gy: (ny (p+1)) x cols, gx: (nx (p+1)) x rows
+  T *gy, *gx;
 };
 
 template <typename T>

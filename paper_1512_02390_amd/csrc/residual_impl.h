@@ -2,9 +2,10 @@
 // residual_inst_*.hip.
 #pragma once
 // Sum-factorised SEM residual r = f - A u (Section 2, tensor-product
-// operator; Section 4 for the variable-coefficient operator B(nu)).
+// operator), and further down the two-pass residual of the variable-
+// coefficient operator B(nu) (Section 4).
 //
-// Work decomposition: one 64-lane wavefront per (strip of NE = 64/p
+// Poisson work decomposition: one 64-lane wavefront per (strip of NE = 64/p
 // consecutive elements in x) x (one element row in y).  Every element owns the
 // nodes [e p, e p + p) in each direction; the shared left/bottom node also
 // receives the contribution of the neighbouring element, recomputed here so
@@ -57,26 +58,6 @@ __device__ __forceinline__ void rows_apply(const T *__restrict__ Op, const T (&x
   for (int o = 0; o < nout; ++o) out[o * ostride] = s * udot<T, P + 1>(Op + o * (P + 1), x);
 }
 
-// Variable-coefficient flux of one element segment: v[a] = w_a nu_a (D seg)[a],
-// computed through the lane's private LDS slot pv; nuw_at(a) gives the
-// product w_a nu_a at local node a (a nodal table with the GLL weight of the
-// contraction direction folded in, read on the fly to keep register pressure
-// low).
-template <typename T, int P, typename NuAt>
-__device__ __forceinline__ void nu_flux(const T *__restrict__ D, const T (&seg)[P + 1],
-                                        NuAt nuw_at, T *pv, T (&v)[P + 1]) {
-  rows_apply<T, P>(D, seg, T(1), pv, 1, P + 1);
-#pragma unroll
-  for (int a = 0; a <= P; ++a) v[a] = pv[a] * nuw_at(a);
-}
-
-// s * (row P of a uniform table) . x through the rolled loop (one row).
-template <typename T, int P>
-__device__ __forceinline__ T last_row(const T *__restrict__ Op, const T (&x)[P + 1], T s, T *pv) {
-  rows_apply<T, P>(opaque(Op) + P * (P + 1), x, s, pv, 1, 1);
-  return pv[0];
-}
-
 // Load a node-array segment of P+1 consecutive nodes along a row or a column.
 template <typename T, int P>
 __device__ __forceinline__ void load_col(const T *__restrict__ u, int row0, int col, const Grid &g,
@@ -101,7 +82,7 @@ __device__ __forceinline__ T coef_value(const T *__restrict__ a, int row, int co
   return a[(long)row * cols + col];
 }
 
-template <typename T, int P, bool NU>
+template <typename T, int P>
 __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
@@ -112,21 +93,6 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   constexpr bool kAlias = P <= 16;
   __shared__ T su[P][LW];                         // owned rows, halo p left, 1 right
   __shared__ T sxp_own[kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
-  __shared__ T spv[NU ? 64 : 1][NU ? P + 2 : 1];  // private flux slots (variable nu)
-  // Variable nu with long rows: D and D^T are read from LDS (broadcast reads)
-  // instead of through the scalar cache, which the two tables overflow.
-  constexpr bool kOpLds = NU && P >= 16;
-  __shared__ T sop[kOpLds ? 2 * (P + 1) * (P + 1) : 1];
-  const T *Dm = A.D, *DTm = A.DT;
-  if constexpr (kOpLds) {
-    for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += 64) {
-      sop[i] = A.D[i];
-      sop[(P + 1) * (P + 1) + i] = A.DT[i];
-    }
-    Dm = sop;
-    DTm = sop + (P + 1) * (P + 1);
-    __syncthreads();
-  }
   const Grid g = A.g;
   const int per = g.periodic;
   const int lane = threadIdx.x;
@@ -136,7 +102,6 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   const int r0 = ey * P;
   const int eym = per ? wrap(ey - 1, g.ny) : ey - 1;
   const bool has_below = per || ey > 0;
-  T *pv = &spv[NU ? lane : 0][0];   // always an LDS address (ds_ instructions)
   auto sxp = [&](int a, int c) -> T & {
     if constexpr (kAlias) return su[a][c];
     else return sxp_own[a][c];
@@ -148,8 +113,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   // last column needed by this strip: the right end of its last element
   const int last_col = min(c0 + W, g.nx * P);
   const bool col_lane = c < W && gc <= last_col;
-  const int gcs = col_lane ? gc : 0;  // a safe column for idle lanes
-  T yv[P + 1];     // y-direction input: the u segment, or its flux for variable nu
+  T yv[P + 1];     // the column's u segment
   load_col<T, P>(A.u, r0, gc, g, col_lane, yv);
   if (col_lane) {
 #pragma unroll
@@ -167,21 +131,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   if (has_below) {
     T seg[P + 1];
     load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
-    if constexpr (NU) {
-      T v[P + 1];
-      nu_flux<T, P>(Dm, seg,
-                    [&](int b) { return coef_value(A.nu, r0 - P + b, gcs, g.rows, g.cols, per); }, pv, v);
-      extra_y = last_row<T, P>(DTm, v, A.sy[eym], pv);
-    } else {
-      extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
-    }
-  }
-  if constexpr (NU) {
-    T v[P + 1];
-    nu_flux<T, P>(Dm, yv,
-                  [&](int b) { return coef_value(A.nu, r0 + b, gcs, g.rows, g.cols, per); }, pv, v);
-#pragma unroll
-    for (int b = 0; b <= P; ++b) yv[b] = v[b];
+    extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
   }
   __syncthreads();
 
@@ -204,29 +154,11 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     if constexpr (kAlias) __syncthreads();   // the results overwrite su below
     if (xlane) {
       T *xrow = &sxp(a, q * P);
-      if constexpr (NU) {
-        T v[P + 1];
-        nu_flux<T, P>(Dm, seg,
-                      [&](int b) { return coef_value(A.nuT, c0 + q * P + b, r0 + a, g.cols, g.rows, per); },
-                      pv, v);
-        rows_apply<T, P>(DTm, v, A.sx[ex], xrow, 1, P);
-      } else {
-        rows_apply<T, P>(A.Lhat, seg, A.sx[ex], xrow, 1, P);
-      }
+      rows_apply<T, P>(A.Lhat, seg, A.sx[ex], xrow, 1, P);
       if (has_left) {
         // contribution of the left neighbour to the shared left node
         auto extra_of = [&](const T(&sl)[P + 1]) -> T {
-          if constexpr (NU) {
-            T v[P + 1];
-            nu_flux<T, P>(Dm, sl,
-                          [&](int b) {
-                            return coef_value(A.nuT, c0 + q * P - P + b, r0 + a, g.cols, g.rows, per);
-                          },
-                          pv, v);
-            return last_row<T, P>(DTm, v, A.sx[exm], pv);
-          } else {
-            return A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), sl);
-          }
+          return A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), sl);
         };
         if constexpr (kAlias) {
           xrow[0] += extra_of(segl);
@@ -248,7 +180,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const T *__restrict__ Op = NU ? DTm : A.Lhat;
+    const T *__restrict__ Op = A.Lhat;
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
     for (int a = 0; a < P; ++a) {
@@ -269,16 +201,171 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
   }
 }
+// ---------------------------------------------------------------------------
+// Variable-coefficient residual in two passes (Section 4, operator B(nu)):
+// B(nu) u = sum over elements of D_y^T G_y + D_x^T G_x with the fluxes
+// G_y = w nu (D_y u) and G_x = w nu (D_x u) per element.  Pass 1 forms every
+// flux exactly once; pass 2 contracts them with D^T and assembles, each node
+// owned by one wavefront as in k_residual.  Flux layouts:
+//   gy[(ey (p+1) + b) * cols + col]: element row ey, local row b, node column;
+//   gx[(ex (p+1) + c) * rows + row]: element column ex, local column c, node
+//   row (transposed, so that one lane per row reads and writes coalesced).
+// ---------------------------------------------------------------------------
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
+  constexpr int NE = 64 / P;
+  constexpr int W = NE * P;
+  __shared__ T su[P][W + 1];   // owned rows of the strip and its right end
+  const Grid g = A.g;
+  const int per = g.periodic;
+  const int lane = threadIdx.x;
+  const int e0 = blockIdx.x * NE;
+  const int ey = blockIdx.y;
+  const int c0 = e0 * P;
+  const int r0 = ey * P;
+  const int last_col = min(c0 + W, g.nx * P);
+  // ---- y flux, lane = node column --------------------------------------------
+  {
+    const int c = lane;
+    const int gc = c0 + c;
+    // columns of the strip up to its right end are staged; the periodic end
+    // column (index cols, node 0) is staged but owns no flux column
+    const bool col_lane = c < W && gc <= last_col;
+    T seg[P + 1];
+    load_col<T, P>(A.u, r0, gc, g, col_lane, seg);
+    if (col_lane) {
+#pragma unroll
+      for (int a = 0; a < P; ++a) su[a][c] = seg[a];
+    }
+    if (col_lane && gc < g.cols) {
+      T *out = A.gy + (long)ey * (P + 1) * g.cols + gc;
+#pragma unroll rows_per_iter<T, P>()
+      for (int b = 0; b <= P; ++b)
+        out[(long)b * g.cols] = udot<T, P + 1>(A.D + b * (P + 1), seg) *
+                                coef_value(A.nu, r0 + b, gc, g.rows, g.cols, per);
+    }
+    // right end of the strip (first column of the next strip)
+    if (lane < P && c0 + W <= last_col)
+      su[lane][W] = node_value(A.u, r0 + lane, c0 + W, g.rows, g.cols, per);
+  }
+  __syncthreads();
+  // ---- x flux, lane = (row a, element q) -------------------------------------
+  {
+    const int q = lane / P, a = lane - (lane / P) * P;
+    const int ex = e0 + q;
+    if (lane < W && ex < g.nx) {
+      T seg[P + 1];
+#pragma unroll
+      for (int d = 0; d <= P; ++d) seg[d] = su[a][q * P + d];
+      const int row = r0 + a;
+      T *out = A.gx + (long)ex * (P + 1) * g.rows + row;
+#pragma unroll rows_per_iter<T, P>()
+      for (int c = 0; c <= P; ++c)
+        out[(long)c * g.rows] = udot<T, P + 1>(A.D + c * (P + 1), seg) *
+                                coef_value(A.nuT, ex * P + c, row, g.cols, g.rows, per);
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
+  constexpr int NE = 64 / P;
+  constexpr int W = NE * P;
+  __shared__ T sxp[P][W];   // x-part per owned node
+  const Grid g = A.g;
+  const int per = g.periodic;
+  const int lane = threadIdx.x;
+  const int e0 = blockIdx.x * NE;
+  const int ey = blockIdx.y;
+  const int c0 = e0 * P;
+  const int r0 = ey * P;
+  const int eym = per ? wrap(ey - 1, g.ny) : ey - 1;
+  const bool has_below = per || ey > 0;
+  const int c = lane;
+  const int gc = c0 + c;
+  const int last_col = min(c0 + W, g.nx * P);
+  const bool col_lane = c < W && gc <= last_col;
+  const int gcs = (col_lane && gc < g.cols) ? gc : c0;   // an existing column
+  // y-direction fluxes of this element row's column, and the element below's
+  // contribution to the shared bottom node
+  T yv[P + 1];
+  {
+    const T *gy = A.gy + (long)ey * (P + 1) * g.cols + gcs;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) yv[b] = gy[(long)b * g.cols];
+  }
+  T extra_y = T(0);
+  if (has_below) {
+    T v[P + 1];
+    const T *gy = A.gy + (long)eym * (P + 1) * g.cols + gcs;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) v[b] = gy[(long)b * g.cols];
+    extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.DT) + P * (P + 1), v);
+  }
+  // ---- x-part, lane = (row a, element q) -------------------------------------
+  {
+    const int q = lane / P, a = lane - (lane / P) * P;
+    const int ex = e0 + q;
+    if (lane < W && ex < g.nx) {
+      const int row = r0 + a;
+      T v[P + 1];
+      {
+        const T *gx = A.gx + (long)ex * (P + 1) * g.rows + row;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) v[b] = gx[(long)b * g.rows];
+      }
+      rows_apply<T, P>(A.DT, v, A.sx[ex], &sxp[a][q * P], 1, P);
+      if (per || ex > 0) {
+        const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
+        const T *gx = A.gx + (long)exm * (P + 1) * g.rows + row;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) v[b] = gx[(long)b * g.rows];
+        sxp[a][q * P] += A.sx[exm] * udot<T, P + 1>(opaque(A.DT) + P * (P + 1), v);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- y-part combined with the x-part and the assembled mass (lane = column) ----
+  const int q = c / P, al = c - (c / P) * P;
+  const int ex = e0 + q;
+  if (col_lane && ex < g.nx) {
+    const bool has_left = per || ex > 0;
+    const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
+    const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
+    const T sy = A.sy[ey];
+#pragma unroll rows_per_iter<T, P>()
+    for (int a = 0; a < P; ++a) {
+      T yp = sy * udot<T, P + 1>(A.DT + a * (P + 1), yv);
+      if (a == 0) yp += extra_y;
+      const int row = r0 + a;
+      const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
+      const T au = myr * sxp[a][c] + mxc * yp;
+      T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
+      if (!per && (row == 0 || gc == 0)) v = T(0);
+      A.out[(long)row * g.cols + gc] = v;
+    }
+    if (!per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
+  }
+  if (!per && lane == 0 && e0 + NE >= g.nx) {
+#pragma unroll
+    for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
+    if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
+  }
+}
+
 }  // namespace
 
 template <typename T, int P>
 void launch_residual_p(const ResidualArgs<T> &a, hipStream_t s) {
   constexpr int NE = 64 / P;
   dim3 grid(ceil_div(a.g.nx, NE), a.g.ny);
-  if (a.nu)
-    hipLaunchKernelGGL((k_residual<T, P, true>), grid, dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_residual<T, P, false>), grid, dim3(64), 0, s, a);
+  if (a.nu) {
+    hipLaunchKernelGGL((k_flux<T, P>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_residual_nu<T, P>), grid, dim3(64), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_residual<T, P>), grid, dim3(64), 0, s, a);
+  }
 }
 
 }  // namespace sem
