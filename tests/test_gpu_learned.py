@@ -60,13 +60,19 @@ def _solve(s, fn, kind="mg11"):
 
 
 def test_learned_parameters_beat_the_paper_on_held_out_problem(trained):
-    from paper_1512_02390_amd.sem import Solver
+    from paper_1512_02390_amd.sem import SemError, Solver
     learned, net, *_ = trained
     xb, yb, p = _problem()
     NU = learned.nodal_nu(xb, yb, p, 0, W.GaussianFieldNu())
     fn = W.random_nodal(NU.shape, 0, W.SEED_RHS)
     paper = Solver(xb, yb, p, 0, 1, 1, 5, nu=NU)
-    it_p, ok_p, om_p, ov_p = _solve(paper, fn)
+    ov_p = [0] + [paper.level_info(l)[1] for l in range(1, paper.L + 1)]
+    try:
+        it_p, ok_p, om_p, ov_p = _solve(paper, fn)
+    except SemError:
+        # the paper's parameters stagnate on this problem; rounding can tip
+        # the iteration into overflow: no reduction at all
+        it_p, ok_p, om_p = 300, False, math.inf
     paper.close()
     s, params = learned.solver_with_learned(xb, yb, p, 0, NU, net)
     assert params is not None
