@@ -1,0 +1,196 @@
+"""GPU parity at the full workload sizes, in the configuration the benchmark
+times (same meshes, orders, overlaps, weights, smoothing schedules, FP64).
+
+  c1, c2, c3, c4: the residual and one V-cycle of the finest level element by
+  element against the oracle (1e-12 / 1e-11 relative to the largest entry),
+  and the MGCG solve to 1e-10: the same iteration count as the oracle and a
+  true FP64 residual (recomputed by the oracle) of at most 1e-10 r_0;
+  c5 (2.4M unknowns, p = 32, variable nu): the residual element by element;
+  one Schwarz sweep checked on sampled subdomains, at the nodes no other
+  subdomain reaches (there the update is that one subdomain's weighted local
+  solve, which the oracle forms by a dense solve); the MGCG solve through its
+  true residual.
+  Mixed precision at c3 size: the FP64 stopping rule holds for the true
+  residual.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from parity_cases import rel_err
+from paper_1512_02390_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _schedule(cfg, L):
+    if cfg.variable_nu:
+        return [1] * (L + 1), [1] * (L + 1)      # MGCG(1,1), as benchmarked
+    return [1] * (L + 1), [0] * (L + 1)          # MG(1,0) / MGCG(1,0)
+
+
+def _nu(cfg, p):
+    if not cfg.variable_nu:
+        return None
+    from oracle.discretization import Space
+    top = Space(cfg.xb, cfg.yb, p, cfg.bc)
+    return W.nodal(W.GaussianFieldNu().nu, top.x(), top.y())
+
+
+def _gpu(cfg, NU, precision=0):
+    from paper_1512_02390_amd.sem import Solver
+    return Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
+                  precision=precision)
+
+
+@pytest.fixture(scope="module", params=["c1", "c2", "c3", "c4"])
+def full(request):
+    from oracle.multigrid import Multigrid
+    cfg = W.config(request.param)
+    print(f"[gpu-fullsize] {cfg.name}: {cfg.description}", flush=True)
+    NU = _nu(cfg, cfg.p)
+    mg = Multigrid(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, NU=NU)
+    gpu = _gpu(cfg, NU)
+    yield cfg, mg, gpu
+    gpu.close()
+
+
+def test_fullsize_residual_and_vcycle(full):
+    cfg, mg, gpu = full
+    sp = mg.spaces[-1]
+    U = W.random_guess(sp.shape, cfg.bc, 70)
+    F = W.random_nodal(sp.shape, cfg.bc, 71)
+    r = gpu.zeros()
+    gpu.residual(mg.L, _dev(U), _dev(F), r)
+    err = rel_err(_host(r), mg.residual(mg.L, U, F))
+    print(f"  residual rel. error {err:.1e}")
+    assert err < 1e-12
+    ns1, ns2 = _schedule(cfg, mg.L)
+    ref = mg.vcycle(U, F, ns1, ns2)
+    u = _dev(U)
+    gpu.vcycle(u, _dev(F), ns1, ns2)
+    err = rel_err(_host(u), ref)
+    print(f"  V-cycle rel. error {err:.1e}")
+    assert err < 1e-11
+
+
+def test_fullsize_mgcg(full):
+    from oracle.mgcg import mgcg
+    cfg, mg, gpu = full
+    sp = mg.spaces[-1]
+    if cfg.name == "c1":
+        fn = W.nodal(lambda x, y: -W.SineSolution().laplacian(x, y), sp.x(), sp.y())
+    else:
+        fn = W.random_nodal(sp.shape, cfg.bc, W.SEED_RHS)
+    F = sp.mass(fn)
+    U0 = W.random_guess(sp.shape, cfg.bc, W.SEED_U0)
+    ns1, ns2 = _schedule(cfg, mg.L)
+    _, _, it_ref = mgcg(mg, U0, F, 200, 1e-10, ns1, ns2)
+    u = _dev(U0)
+    it, hist, ok = gpu.pcg_solve(u, _dev(F), 200, 1e-10, ns1, ns2)
+    Ug = _host(u)
+    r0 = np.linalg.norm(mg.residual(mg.L, U0, F)[sp.mask])
+    rt = np.linalg.norm(mg.residual(mg.L, Ug, F)[sp.mask])
+    print(f"  MGCG {it} iterations (oracle {it_ref}), true residual ratio {rt / r0:.2e}")
+    assert ok and it == it_ref
+    assert rt <= 1.001e-10 * r0
+
+
+@pytest.fixture(scope="module")
+def c5():
+    from oracle.discretization import Space, element_mean
+    cfg = W.config("c5")
+    print(f"[gpu-fullsize] c5: {cfg.description}", flush=True)
+    NU = _nu(cfg, cfg.p)
+    top = Space(cfg.xb, cfg.yb, cfg.p, cfg.bc)
+    gpu = _gpu(cfg, NU)
+    yield cfg, top, NU, element_mean(top, NU), gpu
+    gpu.close()
+
+
+def test_c5_residual(c5):
+    cfg, top, NU, _, gpu = c5
+    U = W.random_guess(top.shape, cfg.bc, 72)
+    F = W.random_nodal(top.shape, cfg.bc, 73)
+    r = gpu.zeros()
+    gpu.residual(gpu.L, _dev(U), _dev(F), r)
+    ref = top.zero_boundary(F - top.apply_B(U, NU))
+    err = rel_err(_host(r), ref)
+    print(f"  c5 residual rel. error {err:.1e}")
+    assert err < 1e-12
+
+
+def test_c5_schwarz_sweep_on_sampled_subdomains(c5):
+    from oracle.schwarz import Subdomain1D, local_matrix
+    cfg, top, NU, nubar, gpu = c5
+    p = cfg.p
+    n_o = gpu.level_info(gpu.L)[1]
+    U = W.random_guess(top.shape, cfg.bc, 74)
+    F = W.random_nodal(top.shape, cfg.bc, 75)
+    u = _dev(U)
+    gpu.schwarz_smooth(gpu.L, u, _dev(F), 1)
+    dU = _host(u) - U
+    R = top.zero_boundary(F - top.apply_B(U, NU))
+    # nodes of element e reached by no other subdomain: local indices
+    # n_o + 1 .. p - n_o - 1 (the neighbours reach n_o nodes into it)
+    lo, hi = n_o + 1, p - n_o - 1
+    for ey, ex in [(1, 1), (20, 7), (33, 46), (46, 24)]:
+        sy = Subdomain1D(top.ay, top.Ly, top.My, ey, n_o)
+        sx = Subdomain1D(top.ax, top.Lx, top.Mx, ex, n_o)
+        Rs = R[np.ix_(sy.glob, sx.glob)]
+        D = np.linalg.solve(local_matrix(sy, sx), Rs.ravel()).reshape(Rs.shape) / nubar[ey, ex]
+        Wt = np.outer(sy.weights(5), sx.weights(5))
+        ref = (Wt * D)
+        # map local tile indices to the exclusive block (interior elements:
+        # every tile position is an unknown)
+        ty = np.arange(lo, hi + 1) + n_o
+        tx = np.arange(lo, hi + 1) + n_o
+        got = dU[np.ix_(sy.glob[ty], sx.glob[tx])]
+        err = np.abs(got - ref[np.ix_(ty, tx)]).max() / np.abs(ref).max()
+        print(f"  c5 subdomain ({ey},{ex}) rel. error {err:.1e}")
+        assert err < 1e-11
+
+
+def test_c5_mgcg_true_residual(c5):
+    cfg, top, NU, _, gpu = c5
+    fn = W.random_nodal(top.shape, cfg.bc, W.SEED_RHS)
+    F = top.mass(fn)
+    U0 = W.random_guess(top.shape, cfg.bc, W.SEED_U0)
+    ns1, ns2 = _schedule(cfg, gpu.L)
+    u = _dev(U0)
+    it, hist, ok = gpu.pcg_solve(u, _dev(F), 200, 1e-10, ns1, ns2)
+    Ug = _host(u)
+    r0 = np.linalg.norm(top.zero_boundary(F - top.apply_B(U0, NU))[top.mask])
+    rt = np.linalg.norm(top.zero_boundary(F - top.apply_B(Ug, NU))[top.mask])
+    print(f"  c5 MGCG {it} iterations, true residual ratio {rt / r0:.2e}")
+    assert ok
+    assert rt <= 1.001e-10 * r0
+
+
+def test_c3_mixed_precision_reaches_fp64_rule():
+    from oracle.discretization import Space
+    cfg = W.config("c3")
+    top = Space(cfg.xb, cfg.yb, cfg.p, cfg.bc)
+    F = top.mass(W.random_nodal(top.shape, cfg.bc, W.SEED_RHS))
+    U0 = W.random_guess(top.shape, cfg.bc, W.SEED_U0)
+    r0 = np.linalg.norm(top.zero_boundary(F - top.apply_A(U0))[top.mask])
+    for prec, name in ((1, "fp32"), (2, "bf16")):
+        print(f"[gpu-fullsize] c3 {name}", flush=True)
+        gpu = _gpu(cfg, None, prec)
+        u = _dev(U0)
+        it, hist, ok = gpu.pcg_solve(u, _dev(F), 200, 1e-10)
+        gpu.close()
+        rt = np.linalg.norm(top.zero_boundary(F - top.apply_A(_host(u)))[top.mask])
+        print(f"  c3 {name}: {it} iterations, true residual ratio {rt / r0:.2e}")
+        assert ok and rt <= 2e-10 * r0
