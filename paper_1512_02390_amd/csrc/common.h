@@ -34,6 +34,16 @@ __device__ __forceinline__ const T *opaque(const T *p) {
   return p;
 }
 
+// Read-only operator tables viewed through the constant address space: the
+// compiler then fetches wave-uniform rows with scalar loads even in kernels
+// that store to global memory (which it cannot otherwise prove disjoint).
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)(p);
+}
+
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace sem

@@ -32,7 +32,7 @@ namespace {
 // Dot product of a wave-uniform matrix row (scalar-register operands) with a
 // register-resident segment, in two interleaved chains.
 template <typename T, int N>
-__device__ __forceinline__ T udot(const T *__restrict__ row, const T (&x)[N]) {
+__device__ __forceinline__ T udot(cptr<T> row, const T (&x)[N]) {
   T a0 = T(0), a1 = T(0);
 #pragma unroll
   for (int i = 0; i + 1 < N; i += 2) {
@@ -52,7 +52,7 @@ template <typename T, int P>
 constexpr int rows_per_iter() { return (P + 1) * (int)sizeof(T) <= 128 ? 2 : 1; }
 
 template <typename T, int P>
-__device__ __forceinline__ void rows_apply(const T *__restrict__ Op, const T (&x)[P + 1], T s,
+__device__ __forceinline__ void rows_apply(cptr<T> Op, const T (&x)[P + 1], T s,
                                            T *out, int ostride, int nout) {
 #pragma unroll rows_per_iter<T, P>()
   for (int o = 0; o < nout; ++o) out[o * ostride] = s * udot<T, P + 1>(Op + o * (P + 1), x);
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   if (has_below) {
     T seg[P + 1];
     load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
-    extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), seg);
+    extra_y = A.sy[eym] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), seg);
   }
   __syncthreads();
 
@@ -154,11 +154,11 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     if constexpr (kAlias) __syncthreads();   // the results overwrite su below
     if (xlane) {
       T *xrow = &sxp(a, q * P);
-      rows_apply<T, P>(A.Lhat, seg, A.sx[ex], xrow, 1, P);
+      rows_apply<T, P>(as_const(A.Lhat), seg, A.sx[ex], xrow, 1, P);
       if (has_left) {
         // contribution of the left neighbour to the shared left node
         auto extra_of = [&](const T(&sl)[P + 1]) -> T {
-          return A.sx[exm] * udot<T, P + 1>(opaque(A.Lhat) + P * (P + 1), sl);
+          return A.sx[exm] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), sl);
         };
         if constexpr (kAlias) {
           xrow[0] += extra_of(segl);
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const T *__restrict__ Op = A.Lhat;
+    const cptr<T> Op = as_const(A.Lhat);
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
     for (int a = 0; a < P; ++a) {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
       T *out = A.gy + (long)ey * (P + 1) * g.cols + gc;
 #pragma unroll rows_per_iter<T, P>()
       for (int b = 0; b <= P; ++b)
-        out[(long)b * g.cols] = udot<T, P + 1>(A.D + b * (P + 1), seg) *
+        out[(long)b * g.cols] = udot<T, P + 1>(as_const(A.D) + b * (P + 1), seg) *
                                 coef_value(A.nu, r0 + b, gc, g.rows, g.cols, per);
     }
     // right end of the strip (first column of the next strip)
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
       T *out = A.gx + (long)ex * (P + 1) * g.rows + row;
 #pragma unroll rows_per_iter<T, P>()
       for (int c = 0; c <= P; ++c)
-        out[(long)c * g.rows] = udot<T, P + 1>(A.D + c * (P + 1), seg) *
+        out[(long)c * g.rows] = udot<T, P + 1>(as_const(A.D) + c * (P + 1), seg) *
                                 coef_value(A.nuT, ex * P + c, row, g.cols, g.rows, per);
     }
   }
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
     const T *gy = A.gy + (long)eym * (P + 1) * g.cols + gcs;
 #pragma unroll
     for (int b = 0; b <= P; ++b) v[b] = gy[(long)b * g.cols];
-    extra_y = A.sy[eym] * udot<T, P + 1>(opaque(A.DT) + P * (P + 1), v);
+    extra_y = A.sy[eym] * udot<T, P + 1>(as_const(A.DT) + P * (P + 1), v);
   }
   // ---- x-part, lane = (row a, element q) -------------------------------------
   {
@@ -315,13 +315,13 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
 #pragma unroll
         for (int b = 0; b <= P; ++b) v[b] = gx[(long)b * g.rows];
       }
-      rows_apply<T, P>(A.DT, v, A.sx[ex], &sxp[a][q * P], 1, P);
+      rows_apply<T, P>(as_const(A.DT), v, A.sx[ex], &sxp[a][q * P], 1, P);
       if (per || ex > 0) {
         const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
         const T *gx = A.gx + (long)exm * (P + 1) * g.rows + row;
 #pragma unroll
         for (int b = 0; b <= P; ++b) v[b] = gx[(long)b * g.rows];
-        sxp[a][q * P] += A.sx[exm] * udot<T, P + 1>(opaque(A.DT) + P * (P + 1), v);
+        sxp[a][q * P] += A.sx[exm] * udot<T, P + 1>(as_const(A.DT) + P * (P + 1), v);
       }
     }
   }
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
     for (int a = 0; a < P; ++a) {
-      T yp = sy * udot<T, P + 1>(A.DT + a * (P + 1), yv);
+      T yp = sy * udot<T, P + 1>(as_const(A.DT) + a * (P + 1), yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
       const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));

@@ -19,7 +19,7 @@ namespace sem {
 namespace {
 
 template <typename T, int N>
-__device__ __forceinline__ T tdot(const T *__restrict__ row, const T (&x)[N]) {
+__device__ __forceinline__ T tdot(cptr<T> row, const T (&x)[N]) {
   T a0 = T(0), a1 = T(0);
 #pragma unroll
   for (int i = 0; i + 1 < N; i += 2) {
@@ -64,8 +64,8 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
       segb[a] = (colok && has_below && a < PF) ? node_value(rf, r0 - PF + a, col, gf.rows, gf.cols, per)
                                                : T(0);
 #pragma unroll 1
-    for (int b = 0; b < PC; ++b) st[b][k] = tdot<T, PF + 1>(ET + b * (PF + 1), seg);
-    st[0][k] += tdot<T, PF + 1>(opaque(ET) + PC * (PF + 1), segb);
+    for (int b = 0; b < PC; ++b) st[b][k] = tdot<T, PF + 1>(as_const(ET) + b * (PF + 1), seg);
+    st[0][k] += tdot<T, PF + 1>(as_const(ET) + PC * (PF + 1), segb);
   }
   __syncthreads();
   // ---- x pass: lane = (coarse row b, element q) -----------------------------
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
     const bool zrow = !per && crow == 0;
 #pragma unroll 1
     for (int g = 0; g < PC; ++g) {
-      T v = tdot<T, PF + 1>(ET + g * (PF + 1), seg);
-      if (g == 0) v += tdot<T, PF + 1>(opaque(ET) + PC * (PF + 1), segl);
+      T v = tdot<T, PF + 1>(as_const(ET) + g * (PF + 1), seg);
+      if (g == 0) v += tdot<T, PF + 1>(as_const(ET) + PC * (PF + 1), segl);
       const bool zero = zrow || (!per && ex == 0 && g == 0);
       out[g] = zero ? T(0) : v;
       if (uz) uz[g] = T(0);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void k_prolong(Grid gf, Grid gc, const T *__res
       for (int c = 0; c <= PC; ++c)
         seg[c] = node_value(uc, ey * PC + b, ex * PC + c, gc.rows, gc.cols, per);
 #pragma unroll 1
-      for (int a = 0; a < PF; ++a) st[b][q * PF + a] = tdot<T, PC + 1>(E + a * (PC + 1), seg);
+      for (int a = 0; a < PF; ++a) st[b][q * PF + a] = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
     }
   }
   __syncthreads();
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(64) void k_prolong(Grid gf, Grid gc, const T *__res
       T *out = uf + (long)r0 * gf.cols + col;
 #pragma unroll 1
       for (int a = 0; a < PF; ++a) {
-        const T v = tdot<T, PC + 1>(opaque(E) + a * (PC + 1), seg);
+        const T v = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
         if (per || r0 + a > 0) out[(long)a * gf.cols] += v;
       }
     }
