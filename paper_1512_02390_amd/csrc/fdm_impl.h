@@ -37,7 +37,7 @@ namespace {
 // Dot product of a wave-uniform matrix row (scalar operands) with a
 // register-resident vector, in two interleaved chains.
 template <typename T, int M>
-__device__ __forceinline__ T urow_dot(const T *__restrict__ row, const T (&x)[M]) {
+__device__ __forceinline__ T urow_dot(cptr<T> row, const T (&x)[M]) {
   T a0 = T(0), a1 = T(0);
 #pragma unroll
   for (int i = 0; i + 1 < M; i += 2) {
@@ -74,10 +74,11 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   const Grid g = A.g;
   const int per = g.periodic;
   // wave-uniform factor matrices: every row is read with scalar loads
-  const T *__restrict__ SyT = A.SyT + (long)ty * M * M;   // S_y^T
-  const T *__restrict__ SyW = A.SyW + (long)ty * M * M;   // diag(w_y) S_y
-  const T *__restrict__ Sx = A.Sx + (long)tx * M * M;     // S_x
-  const T *__restrict__ SxT = A.SxT + (long)tx * M * M;   // S_x^T
+  // (constant address space: scalar loads also in the loop that scatters)
+  const cptr<T> SyT = as_const(A.SyT) + (long)ty * M * M;   // S_y^T
+  const cptr<T> SyW = as_const(A.SyW) + (long)ty * M * M;   // diag(w_y) S_y
+  const cptr<T> Sx = as_const(A.Sx) + (long)tx * M * M;     // S_x
+  const cptr<T> SxT = as_const(A.SxT) + (long)tx * M * M;   // S_x^T
   const int row0 = ey * g.p - A.n_o;
   int gc = ex * g.p - A.n_o + j;
   bool vc;
