@@ -679,7 +679,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     h->pq = dalloc<double>(h->pool, n);
     h->pz = dalloc<double>(h->pool, n);
     h->pro = dalloc<double>(h->pool, n);
-    h->partial = dalloc<double>(h->pool, 2 * kRedBlocks);
+    h->partial = dalloc<double>(h->pool, std::max<long>(2 * kRedBlocks, residual_waves(h->lev[L].g)));
     h->scal = dalloc<double>(h->pool, 16);
     HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&h->pin), 2 * sizeof(double),
                          hipHostMallocDefault));
@@ -699,12 +699,15 @@ template <>
 Tables<float> &tabs<float>(Level &L) { return L.tf; }
 
 template <typename T>
-void residual(sem_ctx *h, int l, const T *u, const T *f, T *out) {
+void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x = nullptr,
+              double *dot_res = nullptr) {
   Level &L = h->lev[l];
   Tables<T> &t = tabs<T>(L);
   ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT,
-                    t.gy, t.gx};
+                    t.gy, t.gx, dot_x, dot_x ? h->partial : nullptr};
   launch_residual<T>(a, h->stream);
+  // dot_res = sum of dot_x * out, from the kernel's per-wavefront partial sums
+  if (dot_x) launch_reduce(h->partial, (int)residual_waves(L.g), dot_res, h->stream);
 }
 
 template <typename T>
@@ -1049,8 +1052,7 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     // for it, so the device does not idle during the round trip.  When the
     // test passes, queued work is discarded; u and r are final.
     auto q_and_pq = [&] {
-      residual<double>(h, L, p, nullptr, q);             // q = A p
-      launch_dot(p, q, n, h->partial, sc + 1, st);       // p.q
+      residual<double>(h, L, p, nullptr, q, p, sc + 1);  // q = A p and p.q in one pass
     };
     auto next_direction = [&] {
       precondition(h, r, z, ns1, ns2);

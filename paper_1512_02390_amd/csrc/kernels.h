@@ -43,7 +43,18 @@ struct ResidualArgs {
   // flux scratch of the variable-nu residual (owned by the level):
   // gy: (ny (p+1)) x cols, gx: (nx (p+1)) x rows
   T *gy, *gx;
+  // optional fused dot product: when dot_x is non-null, wavefront b of the
+  // residual kernel writes sum over its owned nodes of dot_x * out to
+  // dot_part[b] (residual_waves() entries, summed by launch_reduce)
+  const T *dot_x;
+  double *dot_part;
 };
+// Number of wavefronts (one per element strip and element row) of the
+// residual kernels on a grid.
+inline long residual_waves(const Grid &g) {
+  const int ne = 64 / g.p;
+  return (long)((g.nx + ne - 1) / ne) * g.ny;
+}
 
 template <typename T>
 struct FdmArgs {
@@ -110,6 +121,8 @@ void launch_dot2(const double *z, const double *r, const double *ro, long n, dou
                  double *res, hipStream_t s);
 // res[0] = sum x
 void launch_sum(const double *x, long n, double *partial, double *res, hipStream_t s);
+// res = sum of partial[0 .. nb) (fixed order).
+void launch_reduce(const double *partial, int nb, double *res, hipStream_t s);
 // x -= res[0] / count on the unknowns of g (mean removal, periodic)
 void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s);
 // alpha = sc[0] / sc[1]; u += alpha p; r -= alpha q; res = sum r^2

@@ -261,6 +261,10 @@ void launch_convert(const Ta *in, Tb *out, long n, double scale, hipStream_t s) 
 template void launch_convert<double, float>(const double *, float *, long, double, hipStream_t);
 template void launch_convert<float, double>(const float *, double *, long, double, hipStream_t);
 
+void launch_reduce(const double *partial, int nb, double *res, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+}
+
 void launch_dot(const double *x, const double *y, long n, double *partial, double *res,
                 hipStream_t s) {
   const int nb = red_blocks(n);

@@ -58,6 +58,13 @@ __device__ __forceinline__ void rows_apply(cptr<T> Op, const T (&x)[P + 1], T s,
   for (int o = 0; o < nout; ++o) out[o * ostride] = s * udot<T, P + 1>(Op + o * (P + 1), x);
 }
 
+// Sum over the 64 lanes of a wavefront, result in every lane.
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
+}
+
 // Load a node-array segment of P+1 consecutive nodes along a row or a column.
 template <typename T, int P>
 __device__ __forceinline__ void load_col(const T *__restrict__ u, int row0, int col, const Grid &g,
@@ -174,6 +181,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
 
   // ---- y-part combined with the x-part and the assembled mass (lane = column) ----
   //   (A u)(row, col) = M_y(row) xpart + M_x(col) ypart
+  double dsum = 0.0;   // fused dot product (see ResidualArgs::dot_x)
   const int q = c / P, al = c - (c / P) * P;
   const int ex = e0 + q;
   if (col_lane && ex < g.nx) {
@@ -192,6 +200,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
       T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
+      if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
     }
     if (!per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
@@ -199,6 +208,10 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
 #pragma unroll
     for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
+  }
+  if (A.dot_x) {
+    dsum = wave_sum64(dsum);
+    if (lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
   }
 }
 // ---------------------------------------------------------------------------
@@ -327,6 +340,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
   }
   __syncthreads();
   // ---- y-part combined with the x-part and the assembled mass (lane = column) ----
+  double dsum = 0.0;   // fused dot product (see ResidualArgs::dot_x)
   const int q = c / P, al = c - (c / P) * P;
   const int ex = e0 + q;
   if (col_lane && ex < g.nx) {
@@ -344,6 +358,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
       T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
+      if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
     }
     if (!per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
@@ -351,6 +366,10 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
 #pragma unroll
     for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
+  }
+  if (A.dot_x) {
+    dsum = wave_sum64(dsum);
+    if (lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
   }
 }
 
