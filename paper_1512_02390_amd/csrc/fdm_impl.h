@@ -107,6 +107,15 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     const T v = A.r[idx];
     X[i] = ok ? v : T(0);
   }
+  // the row of 1/(lambda_y + lambda_x) used in stage 2 (lane = tile row j),
+  // fetched now so that its latency overlaps stage 1
+  const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
+  const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
+  T dv[M <= 32 ? M : 1];
+  if constexpr (M <= 32) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) dv[c] = d[c];
+  }
   // ---- stage 1: T1 = S_y^T R, lane = column j; row a of T1 -> LDS ----------
 #pragma unroll RU
   for (int a = 0; a < M; ++a) {
@@ -117,13 +126,10 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   // ---- stage 2: T2 = T1 S_x, lane = row j, divided by nu_bar (lambda_y + lambda_x)
 #pragma unroll
   for (int b = 0; b < M; ++b) X[b] = tile[j * LS + b];
-  const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
-  const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
   if constexpr (M <= 32) {
-    // the row of 1/(lambda_y + lambda_x) fits in registers next to the tile row
-    T dv[M];
+    // the eigenvalue row sits in registers next to the tile row
 #pragma unroll
-    for (int c = 0; c < M; ++c) dv[c] = d[c] * s;
+    for (int c = 0; c < M; ++c) dv[c] *= s;
 #pragma unroll RU
     for (int c = 0; c < M; ++c) {
       const T v = urow_dot<T, M>(SxT + c * M, X);

@@ -61,3 +61,14 @@ def test_solver_refuses_missing_library(tmp_path):
             sem.load_library(str(tmp_path / "missing.so"))
     finally:
         sem._lib = saved
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode != 0
+    assert "one GPU" in res.stderr
