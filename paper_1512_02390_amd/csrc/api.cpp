@@ -853,16 +853,26 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
 }
 
 // Preconditioner z = MG(0, r) in the handle's precision (FP64 in, FP64 out).
-void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, const int32_t *ns2) {
+// z = MG(0, r).  prepared: the cycle's inputs were already written by the CG
+// update (r in FP32 and a zero initial guess).  dots (mixed precision only):
+// when non-null, dots[0] = z.(r - ro) and dots[1] = z.r come out of the pass
+// that converts z back to FP64.
+void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, const int32_t *ns2,
+                  bool prepared = false, const double *ro = nullptr, double *dots = nullptr) {
   Level &top = h->lev.back();
   const long n = top.n();
   if (h->precision != SEM_FP64) {
-    launch_convert<double, float>(r, top.ff, n, 1.0, h->stream);
-    launch_fill<float>(top.uf, n, 0.0f, h->stream);
+    if (!prepared) {
+      launch_convert<double, float>(r, top.ff, n, 1.0, h->stream);
+      launch_fill<float>(top.uf, n, 0.0f, h->stream);
+    }
     vcycle_impl<float>(h, top.uf, top.ff, ns1, ns2, true);
-    launch_convert<float, double>(top.uf, z, n, 1.0, h->stream);
+    if (dots)
+      launch_convert_dot2(top.uf, z, r, ro, n, h->partial, dots, h->stream);
+    else
+      launch_convert<float, double>(top.uf, z, n, 1.0, h->stream);
   } else {
-    launch_fill<double>(z, n, 0.0, h->stream);
+    if (!prepared) launch_fill<double>(z, n, 0.0, h->stream);
     vcycle_impl<double>(h, z, r, ns1, ns2, true);
   }
 }
@@ -1054,9 +1064,11 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     auto q_and_pq = [&] {
       residual<double>(h, L, p, nullptr, q, p, sc + 1);  // q = A p and p.q in one pass
     };
+    const bool mixed = h->precision != SEM_FP64;
     auto next_direction = [&] {
-      precondition(h, r, z, ns1, ns2);
-      launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
+      // the update below already wrote the cycle's inputs (prepared)
+      precondition(h, r, z, ns1, ns2, true, ro, mixed ? sc + 6 : nullptr);
+      if (!mixed) launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
       launch_cg_direction(sc + 6, sc + 0, p, z, ro, r, n, st);  // beta = z.(r-r_old)/delta
       launch_copy_scalar(sc + 7, sc + 0, st);            // delta = z.r
     };
@@ -1065,7 +1077,9 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     double prev1 = r0, prev2 = 0.0;   // the last two residual norms
     if (!done && imax > 0) q_and_pq();
     for (it = 1; it <= imax && !done; ++it) {
-      launch_cg_update(sc, u, p, r, q, n, h->partial, sc + 2, st);  // alpha = delta / p.q
+      // alpha = delta / p.q; also writes the next cycle's inputs
+      launch_cg_update(sc, u, p, r, q, n, h->partial, sc + 2, st, mixed ? top.ff : nullptr,
+                       mixed ? top.uf : nullptr, mixed ? nullptr : z);
       double *slot = h->pin + (it & 1);
       HIP_OK(hipMemcpyAsync(slot, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_OK(hipEventRecord(h->nev[it & 1], st));

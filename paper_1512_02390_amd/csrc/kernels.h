@@ -127,7 +127,11 @@ void launch_reduce(const double *partial, int nb, double *res, hipStream_t s);
 void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s);
 // alpha = sc[0] / sc[1]; u += alpha p; r -= alpha q; res = sum r^2
 void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
-                      long n, double *partial, double *res, hipStream_t s);
+                      long n, double *partial, double *res, hipStream_t s, float *r32 = nullptr,
+                      float *z32 = nullptr, double *z64 = nullptr);
+// z = (double) z32; res[0] = z.(r - ro), res[1] = z.r.
+void launch_convert_dot2(const float *z32, double *z, const double *r, const double *ro, long n,
+                         double *partial, double *res, hipStream_t s);
 // beta = num[0] / den[0]; p = z + beta p; ro = r
 void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
                          double *ro, const double *r, long n, hipStream_t s);

@@ -171,9 +171,14 @@ __global__ void k_sub_mean(Grid g, double *__restrict__ x, const double *__restr
   if (idx < n) x[idx] -= sum[0] / (double)n;
 }
 
+// u += alpha p, r -= alpha q (alpha = sc[0] / sc[1]), partial sums of r.r;
+// optionally also prepares the next preconditioner call in the same pass:
+// r32 = (float) r, and zeros in z64 or z32 (the V-cycle's initial guess).
 __global__ void k_cg_update(const double *__restrict__ sc, double *__restrict__ u,
                             const double *__restrict__ p, double *__restrict__ r,
-                            const double *__restrict__ q, long n, double *__restrict__ partial) {
+                            const double *__restrict__ q, long n, double *__restrict__ partial,
+                            float *__restrict__ r32, float *__restrict__ z32,
+                            double *__restrict__ z64) {
   __shared__ double red[RT];
   const double alpha = sc[0] / sc[1];
   double s = 0.0;
@@ -182,9 +187,34 @@ __global__ void k_cg_update(const double *__restrict__ sc, double *__restrict__ 
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     s = fma(ri, ri, s);
+    if (r32) r32[i] = (float)ri;
+    if (z32) z32[i] = 0.0f;
+    if (z64) z64[i] = 0.0;
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// z = (double) z32 and the partial sums of z.(r - ro) and z.r (the inputs of
+// the Polak-Ribiere beta) in one pass.
+__global__ void k_convert_dot2(const float *__restrict__ z32, double *__restrict__ z,
+                               const double *__restrict__ r, const double *__restrict__ ro, long n,
+                               double *__restrict__ partial) {
+  __shared__ double red[RT];
+  double s0 = 0.0, s1 = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+    const double zi = (double)z32[i];
+    z[i] = zi;
+    s0 = fma(zi, r[i] - ro[i], s0);
+    s1 = fma(zi, r[i], s1);
+  }
+  s0 = block_sum(s0, red);
+  __syncthreads();
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[kRedBlocks + blockIdx.x] = s1;
+  }
 }
 
 __global__ void k_cg_direction(const double *__restrict__ num, const double *__restrict__ den,
@@ -291,10 +321,19 @@ void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s)
 }
 
 void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
-                      long n, double *partial, double *res, hipStream_t s) {
+                      long n, double *partial, double *res, hipStream_t s, float *r32,
+                      float *z32, double *z64) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RT), 0, s, sc, u, p, r, q, n, partial);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RT), 0, s, sc, u, p, r, q, n, partial, r32, z32,
+                     z64);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+}
+
+void launch_convert_dot2(const float *z32, double *z, const double *r, const double *ro, long n,
+                         double *partial, double *res, hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_convert_dot2, dim3(nb), dim3(RT), 0, s, z32, z, r, ro, n, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(2), dim3(RT), 0, s, partial, nb, res);
 }
 
 void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
