@@ -15,10 +15,10 @@ Printed JSON line (one):
   cpu_baseline the CPU oracle on a bounded sample of the same workload
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload c2] [--n-o 1]
-                       [--precision fp64|mixed|bf16] [--weights paper|learned]
+                       [--precision fp64|mixed|bf16|fp16] [--weights paper|learned]
                        [--no-cpu-baseline]
 
-With --precision mixed / bf16 or --weights learned the line also carries
+With --precision mixed / bf16 / fp16 or --weights learned the line also carries
 `plain_fp64_paper`: the plain method (FP64, the paper's parameters) timed on
 the same workload, and its speedup ratio.  --weights learned first runs the
 parameter sweeps and trains the network (outside the timed region; reported
@@ -42,7 +42,7 @@ FP64_PEAK_TFS = 78.6         # MI355X FP64 vector
 FP32_PEAK_TFS = 157.3        # MI355X FP32 vector
 RIDGE_FP64 = FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
 RIDGE_FP32 = FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
-BF16_PEAK_TFS = 2500.0       # MI355X dense BF16 matrix cores
+BF16_PEAK_TFS = 2500.0       # MI355X dense BF16 (and FP16) matrix cores
 RIDGE_BF16 = BF16_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fdm_traffic.json")
 
@@ -161,9 +161,9 @@ def main():
                     help="overlap rule per level (default: the workload's)")
     ap.add_argument("--overlaps", default=None,
                     help="explicit overlaps of levels 1..L, comma separated")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "bf16"],
-                    help="fp64; mixed: FP32 V-cycle in FP64 MGCG; bf16: as mixed with the "
-                         "subdomain solves of wide tiles on BF16 matrix cores")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "bf16", "fp16"],
+                    help="fp64; mixed: FP32 V-cycle in FP64 MGCG; bf16 / fp16: as mixed with "
+                         "the subdomain solves of wide tiles on BF16 / FP16 matrix cores")
     ap.add_argument("--imax", type=int, default=200)
     ap.add_argument("--cycle", default=None, choices=["mg10", "mg11", "var11"],
                     help="smoothing schedule (default: mg10; mg11 for variable nu)")
@@ -182,7 +182,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1512_02390_amd.sem import FP64, MIXED_BF16, MIXED_FP32
+    from paper_1512_02390_amd.sem import FP64, MIXED_BF16, MIXED_FP16, MIXED_FP32
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -194,7 +194,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
         return
-    prec = {"fp64": FP64, "mixed": MIXED_FP32, "bf16": MIXED_BF16}[args.precision]
+    prec = {"fp64": FP64, "mixed": MIXED_FP32, "bf16": MIXED_BF16,
+            "fp16": MIXED_FP16}[args.precision]
     ovl = None
     if args.overlaps:
         ovl = [0] + [int(v) for v in args.overlaps.split(",")]
@@ -299,7 +300,7 @@ def main():
     nbytes = 3.0 * rows * cols * word
     avg_ms = kms / max(nk, 1)
     ai = flops / nbytes
-    mfma = prec == MIXED_BF16 and m >= 17
+    mfma = prec in (MIXED_BF16, MIXED_FP16) and m >= 17
     ridge = RIDGE_FP64 if prec == FP64 else (RIDGE_BF16 if mfma else RIDGE_FP32)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -337,7 +338,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {FP64: "f64", MIXED_FP32: "f32+f64", MIXED_BF16: "bf16+f32+f64"}[prec],
+        "dtype": {FP64: "f64", MIXED_FP32: "f32+f64", MIXED_BF16: "bf16+f32+f64",
+                  MIXED_FP16: "f16+f32+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": cfg.description, "name": cfg.name, "elements": [cfg.nx, cfg.ny],
                    "p": cfg.p, "dof": n_dof, "solver": f"MGCG {cycle}, w_5",

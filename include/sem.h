@@ -64,8 +64,15 @@ typedef enum {
  * iteration (the coarse solve stays FP64).  SEM_MIXED_BF16 is SEM_MIXED_FP32
  * with the subdomain solves of levels whose subdomain width
  * p_l + 1 + 2 n_o is at least 17 on the matrix cores: BF16 operands, FP32
- * accumulation. */
-typedef enum { SEM_FP64 = 0, SEM_MIXED_FP32 = 1, SEM_MIXED_BF16 = 2 } sem_precision;
+ * accumulation.  SEM_MIXED_FP16 is the same with FP16 operands, each operand
+ * tile scaled by a power of two into FP16's range (3 more significand bits
+ * than BF16, same speed). */
+typedef enum {
+  SEM_FP64 = 0,
+  SEM_MIXED_FP32 = 1,
+  SEM_MIXED_BF16 = 2,
+  SEM_MIXED_FP16 = 3
+} sem_precision;
 
 typedef struct {
   int32_t nx, ny;          /* elements per direction                      */

@@ -719,8 +719,9 @@ void fdm(sem_ctx *h, int l, const T *r, T *u) {
   const bool timed = (l == h->time_level) && h->ev_used + 2 <= h->ev.size();
   if (timed) HIP_OK(hipEventRecord(h->ev[h->ev_used], h->stream));
   if constexpr (std::is_same<T, float>::value) {
-    if (h->precision == SEM_MIXED_BF16 && L.m >= kMfmaMinTile)
-      launch_fdm_bf16(a, h->stream);
+    const bool mfma = h->precision == SEM_MIXED_BF16 || h->precision == SEM_MIXED_FP16;
+    if (mfma && L.m >= kMfmaMinTile)
+      launch_fdm_mfma(a, h->precision == SEM_MIXED_FP16, h->stream);
     else
       launch_fdm<T>(a, h->stream);
   } else {
@@ -922,7 +923,8 @@ sem_status sem_setup(const sem_mesh *mesh, int32_t p, const sem_overlap *overlap
   auto *h = new (std::nothrow) sem_ctx();
   if (!h) return SEM_ENOMEM;
   h->stream = static_cast<hipStream_t>(stream);
-  if (precision != SEM_FP64 && precision != SEM_MIXED_FP32 && precision != SEM_MIXED_BF16) {
+  if (precision != SEM_FP64 && precision != SEM_MIXED_FP32 && precision != SEM_MIXED_BF16 &&
+      precision != SEM_MIXED_FP16) {
     g_setup_err = "unknown precision";
     delete h;
     return SEM_EINVAL;

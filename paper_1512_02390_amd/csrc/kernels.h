@@ -73,10 +73,11 @@ struct FdmArgs {
 
 template <typename T>
 void launch_residual(const ResidualArgs<T> &a, hipStream_t s);
-// FP32 tables and vectors, BF16 matrix-core products with FP32 accumulation
-// (m <= 48); used for tiles of at least kMfmaMinTile nodes.
+// FP32 tables and vectors, BF16 (fp16 = false) or FP16 matrix-core products
+// with FP32 accumulation (m <= 48); used for tiles of at least kMfmaMinTile
+// nodes.
 constexpr int kMfmaMinTile = 17;
-void launch_fdm_bf16(const FdmArgs<float> &a, hipStream_t s);
+void launch_fdm_mfma(const FdmArgs<float> &a, bool fp16, hipStream_t s);
 template <typename T>
 void launch_fdm(const FdmArgs<T> &a, hipStream_t s);
 

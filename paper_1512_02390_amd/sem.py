@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsem.so")
 BC_DIRICHLET, BC_PERIODIC = 0, 1
 W_TOPHAT, W_ARITH = -1, -2
 NO_FIXED, NO_CEIL_P8, NO_FLOOR_P8, NO_CEIL_P2 = 0, 1, 2, 3
-FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
 
 STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EDOM", -3: "SEM_ENOMEM", -4: "SEM_EHIP",
           -5: "SEM_ENOCONV", -6: "SEM_ENAN", -7: "SEM_EUNSUP"}

@@ -185,7 +185,7 @@ def test_c3_mixed_precision_reaches_fp64_rule():
     F = top.mass(W.random_nodal(top.shape, cfg.bc, W.SEED_RHS))
     U0 = W.random_guess(top.shape, cfg.bc, W.SEED_U0)
     r0 = np.linalg.norm(top.zero_boundary(F - top.apply_A(U0))[top.mask])
-    for prec, name in ((1, "fp32"), (2, "bf16")):
+    for prec, name in ((1, "fp32"), (2, "bf16"), (3, "fp16")):
         print(f"[gpu-fullsize] c3 {name}", flush=True)
         gpu = _gpu(cfg, None, prec)
         u = _dev(U0)
