@@ -48,6 +48,30 @@ __device__ __forceinline__ T urow_dot(cptr<T> row, const T (&x)[M]) {
   return a0 + a1;
 }
 
+// The same with the row in LDS (uniform address: one broadcast read per
+// element of the row, returned in order, so the next rows can be in flight).
+template <typename T, int M>
+__device__ __forceinline__ T lrow_dot(const T *row, const T (&x)[M]) {
+  T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int i = 0; i + 1 < M; i += 2) {
+    a0 = fma(row[i], x[i], a0);
+    a1 = fma(row[i + 1], x[i + 1], a1);
+  }
+  if constexpr (M % 2) a0 = fma(row[M - 1], x[M - 1], a0);
+  return a0 + a1;
+}
+
+// Small tiles take their factor matrices from LDS.  With few wavefronts per
+// SIMD, a scalar-register row costs one full cache round trip per row
+// (scalar loads complete out of order, so each use waits for all of them);
+// staging the four matrices once, with vector loads that are all in flight
+// together, costs one round trip per wavefront.  Wide tiles keep the scalar
+// path: there the FMAs dominate and broadcast LDS reads would compete with
+// them for issue slots.
+template <typename T, int M>
+constexpr bool fdm_lds_factors() { return M <= 16; }
+
 // Output rows per loop iteration: two for small tiles, so that the scalar
 // loads of the next factor row overlap the current row's FMAs; one row (the
 // largest set of factor values held in scalar registers) beyond that.
@@ -62,6 +86,8 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   // one tile per element slot; lanes beyond the last slot read slot EPW-1
   // and never write
   __shared__ T lds[EPW * M * LS];
+  constexpr bool LF = fdm_lds_factors<T, M>();
+  __shared__ T fac[LF ? 4 * M * M : 1];   // S_y^T, diag(w_y) S_y, S_x, S_x^T
   const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
   const int ty = task->ty, tx = task->tx, cnt = task->count;
   const int lane = threadIdx.x;
@@ -89,6 +115,14 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     vc = gc >= 1 && gc <= g.cols - 2;
   }
   T *tile = lds + (has_tile ? k : EPW - 1) * M * LS;
+  if constexpr (LF) {
+    const T *src[4] = {A.SyT + (long)ty * M * M, A.SyW + (long)ty * M * M,
+                       A.Sx + (long)tx * M * M, A.SxT + (long)tx * M * M};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = lane; i < M * M; i += 64) fac[q * M * M + i] = src[q][i];
+  }
 
   // ---- gather the residual tile column (branch-free, always in bounds) ----
   T X[M];
@@ -117,10 +151,19 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     for (int c = 0; c < M; ++c) dv[c] = d[c];
   }
   // ---- stage 1: T1 = S_y^T R, lane = column j; row a of T1 -> LDS ----------
+  if constexpr (LF) {
+    __syncthreads();   // factor matrices staged
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const T v = lrow_dot<T, M>(fac + a * M, X);
+      if (has_tile) tile[a * LS + j] = v;
+    }
+  } else {
 #pragma unroll RU
-  for (int a = 0; a < M; ++a) {
-    const T v = urow_dot<T, M>(SyT + a * M, X);
-    if (has_tile) tile[a * LS + j] = v;
+    for (int a = 0; a < M; ++a) {
+      const T v = urow_dot<T, M>(SyT + a * M, X);
+      if (has_tile) tile[a * LS + j] = v;
+    }
   }
   __syncthreads();
   // ---- stage 2: T2 = T1 S_x, lane = row j, divided by nu_bar (lambda_y + lambda_x)
@@ -130,10 +173,18 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     // the eigenvalue row sits in registers next to the tile row
 #pragma unroll
     for (int c = 0; c < M; ++c) dv[c] *= s;
+    if constexpr (LF) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const T v = lrow_dot<T, M>(fac + 3 * M * M + c * M, X);
+        if (has_tile) tile[j * LS + c] = v;
+      }
+    } else {
 #pragma unroll RU
-    for (int c = 0; c < M; ++c) {
-      const T v = urow_dot<T, M>(SxT + c * M, X);
-      if (has_tile) tile[j * LS + c] = v;
+      for (int c = 0; c < M; ++c) {
+        const T v = urow_dot<T, M>(SxT + c * M, X);
+        if (has_tile) tile[j * LS + c] = v;
+      }
     }
 #pragma unroll
     for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c] * dv[c];
@@ -148,10 +199,18 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c];
   }
   // ---- stage 3: T3 = T2 S_x^T ------------------------------------------------------
+  if constexpr (LF) {
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      const T v = lrow_dot<T, M>(fac + 2 * M * M + b * M, X);
+      if (has_tile) tile[j * LS + b] = v;
+    }
+  } else {
 #pragma unroll RU
-  for (int b = 0; b < M; ++b) {
-    const T v = urow_dot<T, M>(Sx + b * M, X);
-    if (has_tile) tile[j * LS + b] = v;
+    for (int b = 0; b < M; ++b) {
+      const T v = urow_dot<T, M>(Sx + b * M, X);
+      if (has_tile) tile[j * LS + b] = v;
+    }
   }
   __syncthreads();
   // ---- stage 4: du = diag(w_y) S_y T3, lane = column j; weighted scatter-add ------
@@ -160,7 +219,11 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
 #pragma unroll RU
   for (int i = 0; i < M; ++i) {
-    const T v = urow_dot<T, M>(SyW + i * M, X);
+    T v;
+    if constexpr (LF)
+      v = lrow_dot<T, M>(fac + M * M + i * M, X);
+    else
+      v = urow_dot<T, M>(SyW + i * M, X);
     int gr = row0 + i;
     bool vr;
     if (per) {
