@@ -31,6 +31,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace sem {
 namespace {
 
@@ -236,11 +238,146 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   }
 }
 
+// Wide tiles: two wavefronts per work item.  Both hold the same lane ->
+// (element slot, tile column/row) map; wave w computes the outputs
+// [w H, min(M, (w + 1) H)) of every stage (H = ceil(M / 2)): rows of T1,
+// columns of T2 and T3, rows of du.  The tile stays in one LDS buffer; a
+// barrier separates every stage's reads of a tile row from the other wave's
+// writes to it.  Twice the wavefronts at half the serial work each: more
+// latency hiding and finer packing onto the SIMDs.  Not for FP64 rows wider
+// than 32 (256 bytes): there the split kernel spills scalar registers and
+// measured slower than one wavefront.
+template <typename T, int M>
+constexpr bool fdm_two_waves() { return M >= 17 && M * (int)sizeof(T) <= 256; }
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+template <typename T, int M>
+constexpr int kRowsPerIter = fdm_rows_per_iter<T, M>();
+
+template <typename T, int M>
+__global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
+  constexpr int EPW = 64 / M;
+  constexpr int LS = M + 1;  // LDS row stride
+  constexpr int H = (M + 1) / 2;
+  __shared__ T lds[EPW * M * LS];
+  const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
+  const int ty = task->ty, tx = task->tx, cnt = task->count;
+  const int lane = threadIdx.x & 63;
+  // wave index, stated uniform so that the halves below are scalar branches
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k = lane / M;
+  const int j = lane - k * M;
+  const bool act = k < cnt;
+  const bool has_tile = k < EPW;
+  const int packed = task->elem[act ? k : 0];
+  const int ey = packed >> 16, ex = packed & 0xffff;
+  const Grid g = A.g;
+  const int per = g.periodic;
+  const cptr<T> SyT = as_const(A.SyT) + (long)ty * M * M;   // S_y^T
+  const cptr<T> SyW = as_const(A.SyW) + (long)ty * M * M;   // diag(w_y) S_y
+  const cptr<T> Sx = as_const(A.Sx) + (long)tx * M * M;     // S_x
+  const cptr<T> SxT = as_const(A.SxT) + (long)tx * M * M;   // S_x^T
+  const int row0 = ey * g.p - A.n_o;
+  int gc = ex * g.p - A.n_o + j;
+  bool vc;
+  if (per) {
+    gc = wrap(gc, g.cols);
+    vc = true;
+  } else {
+    vc = gc >= 1 && gc <= g.cols - 2;
+  }
+  T *tile = lds + (has_tile ? k : EPW - 1) * M * LS;
+  const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
+  const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
+
+  // ---- gather the residual tile column (both waves) --------------------------------
+  T X[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    int gr = row0 + i;
+    bool ok;
+    if (per) {
+      gr += (gr < 0) ? g.rows : 0;
+      gr -= (gr >= g.rows) ? g.rows : 0;
+      ok = act;
+    } else {
+      ok = act && vc && gr >= 1 && gr <= g.rows - 2;
+    }
+    const long idx = ok ? (long)gr * g.cols + gc : 0;
+    const T v = A.r[idx];
+    X[i] = ok ? v : T(0);
+  }
+  // each stage on the wave's half of the outputs, with compile-time bounds
+  auto half = [&](auto body) {
+    if (w == 0)
+      body(ic<0>{}, ic<H>{});
+    else
+      body(ic<H>{}, ic<M>{});
+  };
+  // ---- stage 1: rows a of T1 = S_y^T R (lane = column j) ---------------------------
+  half([&](auto lo, auto hi) {
+#pragma unroll kRowsPerIter<T, M>
+    for (int a = decltype(lo)::value; a < decltype(hi)::value; ++a) {
+      const T v = urow_dot<T, M>(SyT + a * M, X);
+      if (has_tile) tile[a * LS + j] = v;
+    }
+  });
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < M; ++b) X[b] = tile[j * LS + b];   // row j of T1
+  __syncthreads();
+  // ---- stage 2: columns c of T2 = T1 S_x / (nu_bar (lambda_y + lambda_x)) ----------
+  half([&](auto lo, auto hi) {
+#pragma unroll kRowsPerIter<T, M>
+    for (int c = decltype(lo)::value; c < decltype(hi)::value; ++c) {
+      const T v = urow_dot<T, M>(SxT + c * M, X) * (d[c] * s);
+      if (has_tile) tile[j * LS + c] = v;
+    }
+  });
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c];   // row j of T2
+  __syncthreads();
+  // ---- stage 3: columns b of T3 = T2 S_x^T ----------------------------------------
+  half([&](auto lo, auto hi) {
+#pragma unroll kRowsPerIter<T, M>
+    for (int b = decltype(lo)::value; b < decltype(hi)::value; ++b) {
+      const T v = urow_dot<T, M>(Sx + b * M, X);
+      if (has_tile) tile[j * LS + b] = v;
+    }
+  });
+  __syncthreads();
+  // ---- stage 4: rows i of du = diag(w_y) S_y T3 (lane = column j); scatter-add ----
+#pragma unroll
+  for (int a = 0; a < M; ++a) X[a] = tile[a * LS + j];
+  const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
+  half([&](auto lo, auto hi) {
+#pragma unroll kRowsPerIter<T, M>
+    for (int i = decltype(lo)::value; i < decltype(hi)::value; ++i) {
+      const T v = urow_dot<T, M>(SyW + i * M, X);
+      int gr = row0 + i;
+      bool vr;
+      if (per) {
+        gr = wrap(gr, g.rows);
+        vr = true;
+      } else {
+        vr = gr >= 1 && gr <= g.rows - 2;
+      }
+      if (act && vc && vr) atomic_add(&A.u[(long)gr * g.cols + gc], v * wxj);
+    }
+  });
+}
+
 }  // namespace
 
 template <typename T, int M>
 void launch_fdm_m(const FdmArgs<T> &a, hipStream_t s) {
-  if (a.ntasks > 0) hipLaunchKernelGGL((k_fdm<T, M>), dim3(a.ntasks), dim3(64), 0, s, a);
+  if (a.ntasks <= 0) return;
+  if constexpr (fdm_two_waves<T, M>())
+    hipLaunchKernelGGL((k_fdm2<T, M>), dim3(a.ntasks), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_fdm<T, M>), dim3(a.ntasks), dim3(64), 0, s, a);
 }
 
 }  // namespace sem
