@@ -246,9 +246,10 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
 // writes to it.  Twice the wavefronts at half the serial work each: more
 // latency hiding and finer packing onto the SIMDs.  Not for FP64 rows wider
 // than 32 (256 bytes): there the split kernel spills scalar registers and
-// measured slower than one wavefront.
+// measured slower than one wavefront; nor below 9 nodes, where the extra
+// barriers cost more than the shorter chains save.
 template <typename T, int M>
-constexpr bool fdm_two_waves() { return M >= 17 && M * (int)sizeof(T) <= 256; }
+constexpr bool fdm_two_waves() { return M >= 9 && M * (int)sizeof(T) <= 256; }
 
 template <int V>
 using ic = std::integral_constant<int, V>;
@@ -261,6 +262,8 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
   constexpr int LS = M + 1;  // LDS row stride
   constexpr int H = (M + 1) / 2;
   __shared__ T lds[EPW * M * LS];
+  constexpr bool LF = fdm_lds_factors<T, M>();
+  __shared__ T fac[LF ? 4 * M * M : 1];   // S_y^T, diag(w_y) S_y, S_x, S_x^T
   const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
   const int ty = task->ty, tx = task->tx, cnt = task->count;
   const int lane = threadIdx.x & 63;
@@ -288,11 +291,28 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
     vc = gc >= 1 && gc <= g.cols - 2;
   }
   T *tile = lds + (has_tile ? k : EPW - 1) * M * LS;
+  T X[M];
+  if constexpr (LF) {
+    const T *src[4] = {A.SyT + (long)ty * M * M, A.SyW + (long)ty * M * M,
+                       A.Sx + (long)tx * M * M, A.SxT + (long)tx * M * M};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      for (int i = threadIdx.x; i < M * M; i += 128) fac[q * M * M + i] = src[q][i];
+  }
+  // row q of factor matrix f (0: S_y^T, 1: diag(w_y) S_y, 2: S_x, 3: S_x^T)
+  // dotted with the lane's vector, from LDS or scalar registers
+  auto rdot = [&](int f, int q) -> T {
+    if constexpr (LF) {
+      return lrow_dot<T, M>(fac + f * M * M + q * M, X);
+    } else {
+      const cptr<T> base = f == 0 ? SyT : f == 1 ? SyW : f == 2 ? Sx : SxT;
+      return urow_dot<T, M>(base + q * M, X);
+    }
+  };
   const T *__restrict__ d = A.dinv + ((long)ty * A.ntx + tx) * M * M + j * M;
   const T s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : T(1);
 
   // ---- gather the residual tile column (both waves) --------------------------------
-  T X[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     int gr = row0 + i;
@@ -315,11 +335,12 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
     else
       body(ic<H>{}, ic<M>{});
   };
+  if constexpr (LF) __syncthreads();   // factor matrices staged
   // ---- stage 1: rows a of T1 = S_y^T R (lane = column j) ---------------------------
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int a = decltype(lo)::value; a < decltype(hi)::value; ++a) {
-      const T v = urow_dot<T, M>(SyT + a * M, X);
+      const T v = rdot(0, a);
       if (has_tile) tile[a * LS + j] = v;
     }
   });
@@ -331,7 +352,7 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int c = decltype(lo)::value; c < decltype(hi)::value; ++c) {
-      const T v = urow_dot<T, M>(SxT + c * M, X) * (d[c] * s);
+      const T v = rdot(3, c) * (d[c] * s);
       if (has_tile) tile[j * LS + c] = v;
     }
   });
@@ -343,7 +364,7 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int b = decltype(lo)::value; b < decltype(hi)::value; ++b) {
-      const T v = urow_dot<T, M>(Sx + b * M, X);
+      const T v = rdot(2, b);
       if (has_tile) tile[j * LS + b] = v;
     }
   });
@@ -355,7 +376,7 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int i = decltype(lo)::value; i < decltype(hi)::value; ++i) {
-      const T v = urow_dot<T, M>(SyW + i * M, X);
+      const T v = rdot(1, i);
       int gr = row0 + i;
       bool vr;
       if (per) {
