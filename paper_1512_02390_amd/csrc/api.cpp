@@ -760,8 +760,9 @@ void prolong_add(sem_ctx *h, int l, const T *uc, T *uf) {
   launch_prolong<T>(F.g, C.g, uc, uf, tabs<T>(F).E, h->stream);
 }
 
-// u0 = A_0^+ f0 in FP64.
-void coarse_solve64(sem_ctx *h, const double *f0, double *u0) {
+// u0 = A_0^+ f0 in FP64.  u0_clear: u0 is already zero at every node (the
+// restriction of the V-cycle clears it), so only the unknowns are written.
+void coarse_solve64(sem_ctx *h, const double *f0, double *u0, bool u0_clear = false) {
   Level &c = h->lev[0];
   hipStream_t s = h->stream;
   const double *f = f0;
@@ -774,14 +775,13 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0) {
   const int nx = h->cnx, ny = h->cny;
   const long ld = c.g.cols;
   if (nx == 0 || ny == 0) {  // no coarse unknowns (one Dirichlet element)
-    launch_fill<double>(u0, c.n(), 0.0, s);
+    if (!u0_clear) launch_fill<double>(u0, c.n(), 0.0, s);
     return;
   }
+  if (!u0_clear) launch_fill<double>(u0, c.n(), 0.0, s);
   if (h->cMinv) {
-    launch_fill<double>(u0, c.n(), 0.0, s);
     launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
   } else {
-    launch_fill<double>(u0, c.n(), 0.0, s);
     // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T
     launch_gemm(ny, nx, ny, h->cSy, 1, ny, f + h->coff, ld, 1, h->cT1, nx, nullptr, 0, s);
     launch_gemm(ny, nx, nx, h->cT1, nx, 1, h->cSx, nx, 1, h->cT2, nx, h->cDinv, nx, s);
@@ -794,8 +794,10 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0) {
   }
 }
 
-void coarse_solve(sem_ctx *h, const double *f0, double *u0) { coarse_solve64(h, f0, u0); }
-void coarse_solve(sem_ctx *h, const float *f0, float *u0) {
+void coarse_solve(sem_ctx *h, const double *f0, double *u0, bool u0_clear) {
+  coarse_solve64(h, f0, u0, u0_clear);
+}
+void coarse_solve(sem_ctx *h, const float *f0, float *u0, bool) {
   const long n = h->lev[0].n();
   launch_convert<float, double>(f0, h->cf64, n, 1.0, h->stream);
   coarse_solve64(h, h->cf64, h->cu64);
@@ -839,12 +841,15 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
     }
     Level &cl = h->lev[l - 1];
     T *fc = V::f(cl);
-    restrict_<T>(h, l, rr, fc, l - 1 > 0 ? V::u(cl) : nullptr);
+    // the restriction also clears the next level's correction (for level 0
+    // only in FP64: the FP32 cycle solves the coarse problem in an FP64 copy)
+    const bool clear = l - 1 > 0 || std::is_same<T, double>::value;
+    restrict_<T>(h, l, rr, fc, clear ? V::u(cl) : nullptr);
     f[l - 1] = fc;
   }
   // with a single level (p = 1) the cycle is the coarse solve on the caller's array
   if (L > 0) u[0] = V::u(h->lev[0]);
-  coarse_solve(h, f[0], u[0]);
+  coarse_solve(h, f[0], u[0], L > 0);
   for (int l = 1; l <= L; ++l) {
     Level &lv = h->lev[l];
     if (l < L) u[l] = V::u(lv);

@@ -225,14 +225,33 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
 //   row (transposed, so that one lane per row reads and writes coalesced).
 // ---------------------------------------------------------------------------
 
-template <typename T, int P>
-__global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
+// Wavefronts per block of the two variable-coefficient kernels: two from
+// p = 8 on.  The wavefronts hold the same lane map and split the outputs of
+// every loop; the staging into LDS and the boundary writes stay with wave 0.
+// Both kernels run one block per strip and element row, which at these
+// sizes leaves the SIMDs under-occupied with one wavefront per block.
+template <int P>
+constexpr int nu_waves() { return P >= 8 ? 2 : 1; }
+
+// Wave w's share [lo, hi) of n outputs.
+template <int NW>
+__device__ __forceinline__ void share(int n, int w, int &lo, int &hi) {
+  const int h = (n + NW - 1) / NW;
+  lo = min(n, w * h);
+  hi = min(n, lo + h);
+}
+
+template <typename T, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_flux(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
   __shared__ T su[P][W + 1];   // owned rows of the strip and its right end
   const Grid g = A.g;
   const int per = g.periodic;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  int lo, hi;
+  share<NW>(P + 1, w, lo, hi);
   const int e0 = blockIdx.x * NE;
   const int ey = blockIdx.y;
   const int c0 = e0 * P;
@@ -247,19 +266,19 @@ __global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
     const bool col_lane = c < W && gc <= last_col;
     T seg[P + 1];
     load_col<T, P>(A.u, r0, gc, g, col_lane, seg);
-    if (col_lane) {
+    if (col_lane && w == 0) {
 #pragma unroll
       for (int a = 0; a < P; ++a) su[a][c] = seg[a];
     }
     if (col_lane && gc < g.cols) {
       T *out = A.gy + (long)ey * (P + 1) * g.cols + gc;
 #pragma unroll rows_per_iter<T, P>()
-      for (int b = 0; b <= P; ++b)
+      for (int b = lo; b < hi; ++b)
         out[(long)b * g.cols] = udot<T, P + 1>(as_const(A.D) + b * (P + 1), seg) *
                                 coef_value(A.nu, r0 + b, gc, g.rows, g.cols, per);
     }
     // right end of the strip (first column of the next strip)
-    if (lane < P && c0 + W <= last_col)
+    if (w == 0 && lane < P && c0 + W <= last_col)
       su[lane][W] = node_value(A.u, r0 + lane, c0 + W, g.rows, g.cols, per);
   }
   __syncthreads();
@@ -274,21 +293,25 @@ __global__ __launch_bounds__(64) void k_flux(ResidualArgs<T> A) {
       const int row = r0 + a;
       T *out = A.gx + (long)ex * (P + 1) * g.rows + row;
 #pragma unroll rows_per_iter<T, P>()
-      for (int c = 0; c <= P; ++c)
+      for (int c = lo; c < hi; ++c)
         out[(long)c * g.rows] = udot<T, P + 1>(as_const(A.D) + c * (P + 1), seg) *
                                 coef_value(A.nuT, ex * P + c, row, g.cols, g.rows, per);
     }
   }
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
+template <typename T, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
   __shared__ T sxp[P][W];   // x-part per owned node
+  __shared__ double dsum1;  // wave 1's part of the fused dot product
   const Grid g = A.g;
   const int per = g.periodic;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  int lo, hi;
+  share<NW>(P, w, lo, hi);
   const int e0 = blockIdx.x * NE;
   const int ey = blockIdx.y;
   const int c0 = e0 * P;
@@ -300,8 +323,9 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
   const int last_col = min(c0 + W, g.nx * P);
   const bool col_lane = c < W && gc <= last_col;
   const int gcs = (col_lane && gc < g.cols) ? gc : c0;   // an existing column
-  // y-direction fluxes of this element row's column, and the element below's
-  // contribution to the shared bottom node
+  // y-direction fluxes of this element row's column, and (for the wave that
+  // owns output row 0) the element below's contribution to the shared bottom
+  // node
   T yv[P + 1];
   {
     const T *gy = A.gy + (long)ey * (P + 1) * g.cols + gcs;
@@ -309,7 +333,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
     for (int b = 0; b <= P; ++b) yv[b] = gy[(long)b * g.cols];
   }
   T extra_y = T(0);
-  if (has_below) {
+  if (has_below && lo == 0) {
     T v[P + 1];
     const T *gy = A.gy + (long)eym * (P + 1) * g.cols + gcs;
 #pragma unroll
@@ -328,8 +352,9 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
 #pragma unroll
         for (int b = 0; b <= P; ++b) v[b] = gx[(long)b * g.rows];
       }
-      rows_apply<T, P>(as_const(A.DT), v, A.sx[ex], &sxp[a][q * P], 1, P);
-      if (per || ex > 0) {
+      rows_apply<T, P>(as_const(A.DT) + lo * (P + 1), v, A.sx[ex], &sxp[a][q * P + lo], 1,
+                       hi - lo);
+      if (lo == 0 && (per || ex > 0)) {
         const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
         const T *gx = A.gx + (long)exm * (P + 1) * g.rows + row;
 #pragma unroll
@@ -349,7 +374,7 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
-    for (int a = 0; a < P; ++a) {
+    for (int a = lo; a < hi; ++a) {
       T yp = sy * udot<T, P + 1>(as_const(A.DT) + a * (P + 1), yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
@@ -360,16 +385,22 @@ __global__ __launch_bounds__(64) void k_residual_nu(ResidualArgs<T> A) {
       A.out[(long)row * g.cols + gc] = v;
       if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
     }
-    if (!per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
+    if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
-  if (!per && lane == 0 && e0 + NE >= g.nx) {
+  if (w == 0 && !per && lane == 0 && e0 + NE >= g.nx) {
 #pragma unroll
     for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
   }
   if (A.dot_x) {
     dsum = wave_sum64(dsum);
-    if (lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
+    if constexpr (NW > 1) {
+      // wave 0 + wave 1, in that order
+      if (w == 1 && lane == 0) dsum1 = dsum;
+      __syncthreads();
+      if (w == 0) dsum += dsum1;
+    }
+    if (w == 0 && lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
   }
 }
 
@@ -380,8 +411,9 @@ void launch_residual_p(const ResidualArgs<T> &a, hipStream_t s) {
   constexpr int NE = 64 / P;
   dim3 grid(ceil_div(a.g.nx, NE), a.g.ny);
   if (a.nu) {
-    hipLaunchKernelGGL((k_flux<T, P>), grid, dim3(64), 0, s, a);
-    hipLaunchKernelGGL((k_residual_nu<T, P>), grid, dim3(64), 0, s, a);
+    constexpr int NW = nu_waves<P>();
+    hipLaunchKernelGGL((k_flux<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
+    hipLaunchKernelGGL((k_residual_nu<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   } else {
     hipLaunchKernelGGL((k_residual<T, P>), grid, dim3(64), 0, s, a);
   }
