@@ -89,8 +89,26 @@ __device__ __forceinline__ T coef_value(const T *__restrict__ a, int row, int co
   return a[(long)row * cols + col];
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
+// Wavefronts per block of the residual kernels.  With one block per element
+// strip and element row, one wavefront per block leaves the SIMDs under-
+// occupied at these sizes; from p = 8 (Poisson: p = 4) a second wavefront
+// holds the same lane map and takes half of the outputs of every loop, while
+// the staging into LDS and the boundary writes stay with wave 0.
+template <int P>
+constexpr int nu_waves() { return P >= 8 ? 2 : 1; }
+template <int P>
+constexpr int poisson_waves() { return P >= 4 ? 2 : 1; }
+
+// Wave w's share [lo, hi) of n outputs.
+template <int NW>
+__device__ __forceinline__ void share(int n, int w, int &lo, int &hi) {
+  const int h = (n + NW - 1) / NW;
+  lo = min(n, w * h);
+  hi = min(n, lo + h);
+}
+
+template <typename T, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
   constexpr int LW = W + P + 1;
@@ -100,9 +118,14 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   constexpr bool kAlias = P <= 16;
   __shared__ T su[P][LW];                         // owned rows, halo p left, 1 right
   __shared__ T sxp_own[kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
+  __shared__ double dsum1;  // wave 1's part of the fused dot product
   const Grid g = A.g;
   const int per = g.periodic;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  // wave w computes the output rows / x-part columns [lo, hi)
+  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  int lo, hi;
+  share<NW>(P, w, lo, hi);
   const int e0 = blockIdx.x * NE;
   const int ey = blockIdx.y;
   const int c0 = e0 * P;
@@ -122,12 +145,12 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   const bool col_lane = c < W && gc <= last_col;
   T yv[P + 1];     // the column's u segment
   load_col<T, P>(A.u, r0, gc, g, col_lane, yv);
-  if (col_lane) {
+  if (col_lane && w == 0) {
 #pragma unroll
     for (int a = 0; a < P; ++a) su[a][P + c] = yv[a];
   }
   // halo columns of the owned rows
-  if (lane < P || (lane == P && c0 + W <= last_col)) {
+  if (w == 0 && (lane < P || (lane == P && c0 + W <= last_col))) {
     const int k = lane < P ? lane : P + W;
     const int col = lane < P ? c0 - P + lane : c0 + W;
 #pragma unroll
@@ -135,7 +158,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
   }
   // the element below contributes to the shared bottom row (local node P)
   T extra_y = T(0);
-  if (has_below) {
+  if (has_below && lo == 0) {
     T seg[P + 1];
     load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
     extra_y = A.sy[eym] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), seg);
@@ -161,8 +184,8 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     if constexpr (kAlias) __syncthreads();   // the results overwrite su below
     if (xlane) {
       T *xrow = &sxp(a, q * P);
-      rows_apply<T, P>(as_const(A.Lhat), seg, A.sx[ex], xrow, 1, P);
-      if (has_left) {
+      rows_apply<T, P>(as_const(A.Lhat) + lo * (P + 1), seg, A.sx[ex], xrow + lo, 1, hi - lo);
+      if (has_left && lo == 0) {
         // contribution of the left neighbour to the shared left node
         auto extra_of = [&](const T(&sl)[P + 1]) -> T {
           return A.sx[exm] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), sl);
@@ -191,7 +214,7 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
     const cptr<T> Op = as_const(A.Lhat);
     const T sy = A.sy[ey];
 #pragma unroll rows_per_iter<T, P>()
-    for (int a = 0; a < P; ++a) {
+    for (int a = lo; a < hi; ++a) {
       T yp = sy * udot<T, P + 1>(Op + a * (P + 1), yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
@@ -202,16 +225,22 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
       A.out[(long)row * g.cols + gc] = v;
       if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
     }
-    if (!per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
+    if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
-  if (!per && lane == 0 && e0 + NE >= g.nx) {
+  if (w == 0 && !per && lane == 0 && e0 + NE >= g.nx) {
 #pragma unroll
     for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
   }
   if (A.dot_x) {
     dsum = wave_sum64(dsum);
-    if (lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
+    if constexpr (NW > 1) {
+      // wave 0 + wave 1, in that order
+      if (w == 1 && lane == 0) dsum1 = dsum;
+      __syncthreads();
+      if (w == 0) dsum += dsum1;
+    }
+    if (w == 0 && lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
   }
 }
 // ---------------------------------------------------------------------------
@@ -224,22 +253,6 @@ __global__ __launch_bounds__(64) void k_residual(ResidualArgs<T> A) {
 //   gx[(ex (p+1) + c) * rows + row]: element column ex, local column c, node
 //   row (transposed, so that one lane per row reads and writes coalesced).
 // ---------------------------------------------------------------------------
-
-// Wavefronts per block of the two variable-coefficient kernels: two from
-// p = 8 on.  The wavefronts hold the same lane map and split the outputs of
-// every loop; the staging into LDS and the boundary writes stay with wave 0.
-// Both kernels run one block per strip and element row, which at these
-// sizes leaves the SIMDs under-occupied with one wavefront per block.
-template <int P>
-constexpr int nu_waves() { return P >= 8 ? 2 : 1; }
-
-// Wave w's share [lo, hi) of n outputs.
-template <int NW>
-__device__ __forceinline__ void share(int n, int w, int &lo, int &hi) {
-  const int h = (n + NW - 1) / NW;
-  lo = min(n, w * h);
-  hi = min(n, lo + h);
-}
 
 template <typename T, int P, int NW>
 __global__ __launch_bounds__(64 * NW) void k_flux(ResidualArgs<T> A) {
@@ -415,7 +428,8 @@ void launch_residual_p(const ResidualArgs<T> &a, hipStream_t s) {
     hipLaunchKernelGGL((k_flux<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
     hipLaunchKernelGGL((k_residual_nu<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_residual<T, P>), grid, dim3(64), 0, s, a);
+    constexpr int NW = poisson_waves<P>();
+    hipLaunchKernelGGL((k_residual<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   }
 }
 
