@@ -2,8 +2,8 @@
 // level l-1 (order PC = ceil(PF/2)) to level l (order PF) and its transpose.
 // Per element I_l = E_y (x) E_x with E[a][c] = l^c_c(xi^f_a).
 //
-// One 64-lane wavefront per (strip of NE = 64/PF elements in x) x (one
-// element row), sum-factorised in two 1-D passes through LDS.  Every output
+// One block per (strip of NE = 64/PF elements in x) x (one element row), of
+// one or two 64-lane wavefronts, sum-factorised in two 1-D passes through LDS.  Every output
 // node has one owner (the element whose left/bottom half-open range holds it),
 // so no atomics are needed and the result is deterministic.
 //
@@ -17,6 +17,20 @@
 
 namespace sem {
 namespace {
+
+// Wavefronts per block: two from PF = 8 on (one block per element strip and
+// element row leaves the SIMDs under-occupied with one).  Both hold the same
+// lane map; loops over outputs are split, boundary writes stay with wave 0.
+template <int PF>
+constexpr int transfer_waves() { return PF >= 8 ? 2 : 1; }
+
+// Wave w's share [lo, hi) of n outputs.
+template <int NW>
+__device__ __forceinline__ void tshare(int n, int w, int &lo, int &hi) {
+  const int h = (n + NW - 1) / NW;
+  lo = min(n, w * h);
+  hi = min(n, lo + h);
+}
 
 template <typename T, int N>
 __device__ __forceinline__ T tdot(cptr<T> row, const T (&x)[N]) {
@@ -32,8 +46,8 @@ __device__ __forceinline__ T tdot(cptr<T> row, const T (&x)[N]) {
 
 // Restriction.  ET = E^T, (PC+1) x (PF+1).  Also writes zero into uc_zero (the
 // coarse correction) at every coarse node it owns, when uc_zero is non-null.
-template <typename T, int PF>
-__global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__restrict__ rf,
+template <typename T, int PF, int NW>
+__global__ __launch_bounds__(64 * NW) void k_restrict(Grid gf, Grid gc, const T *__restrict__ rf,
                                                  T *__restrict__ fc, T *__restrict__ uc_zero,
                                                  const T *__restrict__ ET) {
   constexpr int PC = (PF + 1) / 2;
@@ -42,7 +56,8 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
   constexpr int LW = W + PF + 1;   // fine columns c0 - PF .. c0 + W
   __shared__ T st[PC][LW];
   const int per = gf.periodic;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const int e0 = blockIdx.x * NE;
   const int ey = blockIdx.y;
   const int c0 = e0 * PF;
@@ -50,7 +65,7 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
   const bool has_below = per || ey > 0;
   const int last_col = min(c0 + W, gf.nx * PF);  // right end of the strip's last element
   // ---- y pass: fine column -> PC coarse rows of this element row ----------
-  for (int k = lane; k < LW; k += 64) {
+  for (int k = threadIdx.x; k < LW; k += 64 * NW) {
     const int col = c0 - PF + k;
     if (col > last_col) break;
     const bool colok = per || col >= 0;
@@ -82,8 +97,10 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
     T *out = fc + (long)crow * gc.cols + ex * PC;
     T *uz = uc_zero ? uc_zero + (long)crow * gc.cols + ex * PC : nullptr;
     const bool zrow = !per && crow == 0;
+    int glo, ghi;
+    tshare<NW>(PC, w, glo, ghi);
 #pragma unroll 1
-    for (int g = 0; g < PC; ++g) {
+    for (int g = glo; g < ghi; ++g) {
       T v = tdot<T, PF + 1>(as_const(ET) + g * (PF + 1), seg);
       if (g == 0) v += tdot<T, PF + 1>(as_const(ET) + PC * (PF + 1), segl);
       const bool zero = zrow || (!per && ex == 0 && g == 0);
@@ -92,7 +109,7 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
     }
   }
   // ---- Dirichlet: the last coarse row and column are boundary nodes ----------
-  if (!per) {
+  if (!per && w == 0) {
     if (ey == gf.ny - 1) {
       for (int cc = lane; cc < NE * PC + 1; cc += 64) {
         const int ccol = e0 * PC + cc;
@@ -111,15 +128,18 @@ __global__ __launch_bounds__(64) void k_restrict(Grid gf, Grid gc, const T *__re
 }
 
 // Prolongation u_f += I u_c.  E is (PF+1) x (PC+1) row-major.
-template <typename T, int PF>
-__global__ __launch_bounds__(64) void k_prolong(Grid gf, Grid gc, const T *__restrict__ uc,
+template <typename T, int PF, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prolong(Grid gf, Grid gc, const T *__restrict__ uc,
                                                 T *__restrict__ uf, const T *__restrict__ E) {
   constexpr int PC = (PF + 1) / 2;
   constexpr int NE = 64 / PF;
   constexpr int W = NE * PF;
   __shared__ T st[PC + 1][W];
   const int per = gf.periodic;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  int alo, ahi;   // this wave's fine outputs a
+  tshare<NW>(PF, w, alo, ahi);
   const int e0 = blockIdx.x * NE;
   const int ey = blockIdx.y;
   const int c0 = e0 * PF;
@@ -134,7 +154,8 @@ __global__ __launch_bounds__(64) void k_prolong(Grid gf, Grid gc, const T *__res
       for (int c = 0; c <= PC; ++c)
         seg[c] = node_value(uc, ey * PC + b, ex * PC + c, gc.rows, gc.cols, per);
 #pragma unroll 1
-      for (int a = 0; a < PF; ++a) st[b][q * PF + a] = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
+      for (int a = alo; a < ahi; ++a)
+        st[b][q * PF + a] = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
     }
   }
   __syncthreads();
@@ -149,7 +170,7 @@ __global__ __launch_bounds__(64) void k_prolong(Grid gf, Grid gc, const T *__res
       for (int b = 0; b <= PC; ++b) seg[b] = st[b][c];
       T *out = uf + (long)r0 * gf.cols + col;
 #pragma unroll 1
-      for (int a = 0; a < PF; ++a) {
+      for (int a = alo; a < ahi; ++a) {
         const T v = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
         if (per || r0 + a > 0) out[(long)a * gf.cols] += v;
       }
@@ -163,16 +184,19 @@ template <typename T, int PF>
 void launch_restrict_p(const Grid &gf, const Grid &gc, const T *rf, T *fc, T *uc_zero,
                        const T *ET, hipStream_t s) {
   constexpr int NE = 64 / PF;
+  constexpr int NW = transfer_waves<PF>();
   dim3 grid(ceil_div(gf.nx, NE), gf.ny);
-  hipLaunchKernelGGL((k_restrict<T, PF>), grid, dim3(64), 0, s, gf, gc, rf, fc, uc_zero, ET);
+  hipLaunchKernelGGL((k_restrict<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, rf, fc, uc_zero,
+                     ET);
 }
 
 template <typename T, int PF>
 void launch_prolong_p(const Grid &gf, const Grid &gc, const T *uc, T *uf, const T *E,
                       hipStream_t s) {
   constexpr int NE = 64 / PF;
+  constexpr int NW = transfer_waves<PF>();
   dim3 grid(ceil_div(gf.nx, NE), gf.ny);
-  hipLaunchKernelGGL((k_prolong<T, PF>), grid, dim3(64), 0, s, gf, gc, uc, uf, E);
+  hipLaunchKernelGGL((k_prolong<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, uc, uf, E);
 }
 
 }  // namespace sem
