@@ -320,8 +320,12 @@ def main():
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic
+    word_t = "double" if prec == FP64 else "float"
+    # the library's dispatch: two wavefronts per work item from m = 9, for
+    # FP64 only while a factor row fits 256 bytes
+    two_waves = m >= 9 and m * (8 if prec == FP64 else 4) <= 256
     kname = (f"k_fdm_mfma<{(m + 15) // 16}> (m={m})" if mfma
-             else f"k_fdm<{'double' if prec == FP64 else 'float'},{m}>")
+             else f"k_fdm{'2' if two_waves else ''}<{word_t},{m}>")
     roof.update({"kernel": kname,
                  "avg_launch_ms": avg_ms, "launches": nk,
                  "algorithmic_flops": flops, "algorithmic_bytes": nbytes,
