@@ -6,10 +6,12 @@
 // diagonalisation of A_ss^{-1} (Lynch-Rice-Thomas), scaled by 1/nu_bar_s for
 // variable diffusion (Section 4).
 //
-// Mapping onto gfx950: one 64-lane wavefront per work item of EPW = 64/m
-// elements that share their subdomain type in x and in y, so the factor
-// matrices S, S^T are wave-uniform and enter every FMA as a scalar-register
-// operand straight from the scalar cache; no LDS traffic for the operators.
+// Mapping onto gfx950: one work item of EPW = 64/m elements that share their
+// subdomain type in x and in y, so the factor matrices S, S^T are wave-
+// uniform: they enter every FMA as scalar-register operands (wide tiles) or
+// as broadcast reads of a copy staged in LDS once per block (m <= 16).  A
+// work item runs on one 64-lane wavefront (k_fdm) or, for mid-size tiles, on
+// two that split every stage's outputs (k_fdm2, further down).
 //   stage 1  lane = tile column j: T1[:, j] = S_y^T r_s[:, j]      (m^2 FMA)
 //   LDS transpose (one m x m tile per element)
 //   stage 2  lane = tile row i:    T2[i, :] = T1[i, :] S_x         (m^2 FMA)

@@ -5,8 +5,10 @@
 // operator), and further down the two-pass residual of the variable-
 // coefficient operator B(nu) (Section 4).
 //
-// Poisson work decomposition: one 64-lane wavefront per (strip of NE = 64/p
-// consecutive elements in x) x (one element row in y).  Every element owns the
+// Poisson work decomposition: one block per (strip of NE = 64/p consecutive
+// elements in x) x (one element row in y), of one or two 64-lane wavefronts
+// with the same lane map (the second takes half of every loop's outputs, see
+// nu_waves / poisson_waves below).  Every element owns the
 // nodes [e p, e p + p) in each direction; the shared left/bottom node also
 // receives the contribution of the neighbouring element, recomputed here so
 // that no two wavefronts write the same node (no atomics, deterministic).
