@@ -134,7 +134,8 @@ struct sem_ctx {
   size_t ev_used = 0;
   std::string err;
   // pinned host slots and events for reading residual norms asynchronously
-  double *pin = nullptr;
+  double *pin = nullptr;                   // 2 slots of kRedBlocks r.r partials (pinned)
+  double *part_rr = nullptr, *part_d2 = nullptr;   // MGCG partial sums (device)
   hipEvent_t nev[2] = {nullptr, nullptr};
   ~sem_ctx() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -681,7 +682,9 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     h->pro = dalloc<double>(h->pool, n);
     h->partial = dalloc<double>(h->pool, std::max<long>(2 * kRedBlocks, residual_waves(h->lev[L].g)));
     h->scal = dalloc<double>(h->pool, 16);
-    HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&h->pin), 2 * sizeof(double),
+    h->part_rr = dalloc<double>(h->pool, kRedBlocks);
+    h->part_d2 = dalloc<double>(h->pool, 2 * kRedBlocks);
+    HIP_OK(hipHostMalloc(reinterpret_cast<void **>(&h->pin), 2 * kRedBlocks * sizeof(double),
                          hipHostMallocDefault));
     for (hipEvent_t &e : h->nev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
@@ -706,8 +709,9 @@ void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x 
   ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT,
                     t.gy, t.gx, dot_x, dot_x ? h->partial : nullptr};
   launch_residual<T>(a, h->stream);
-  // dot_res = sum of dot_x * out, from the kernel's per-wavefront partial sums
-  if (dot_x) launch_reduce(h->partial, (int)residual_waves(L.g), dot_res, h->stream);
+  // dot_res = sum of dot_x * out, from the kernel's per-block partial sums
+  // (without dot_res they stay in h->partial for the consumer to add)
+  if (dot_x && dot_res) launch_reduce(h->partial, (int)residual_waves(L.g), dot_res, h->stream);
 }
 
 template <typename T>
@@ -859,12 +863,12 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
 }
 
 // Preconditioner z = MG(0, r) in the handle's precision (FP64 in, FP64 out).
-// z = MG(0, r).  prepared: the cycle's inputs were already written by the CG
-// update (r in FP32 and a zero initial guess).  dots (mixed precision only):
-// when non-null, dots[0] = z.(r - ro) and dots[1] = z.r come out of the pass
-// that converts z back to FP64.
+// prepared: the cycle's inputs were already written by the CG update (r in
+// FP32 and a zero initial guess).  d2_part (mixed precision only): when
+// non-null, the partial sums of z.(r - ro) and z.r (launch_dot2_partials'
+// layout) come out of the pass that converts z back to FP64.
 void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, const int32_t *ns2,
-                  bool prepared = false, const double *ro = nullptr, double *dots = nullptr) {
+                  bool prepared = false, const double *ro = nullptr, double *d2_part = nullptr) {
   Level &top = h->lev.back();
   const long n = top.n();
   if (h->precision != SEM_FP64) {
@@ -873,8 +877,8 @@ void precondition(sem_ctx *h, const double *r, double *z, const int32_t *ns1, co
       launch_fill<float>(top.uf, n, 0.0f, h->stream);
     }
     vcycle_impl<float>(h, top.uf, top.ff, ns1, ns2, true);
-    if (dots)
-      launch_convert_dot2(top.uf, z, r, ro, n, h->partial, dots, h->stream);
+    if (d2_part)
+      launch_convert_dot2_partials(top.uf, z, r, ro, n, d2_part, h->stream);
     else
       launch_convert<float, double>(top.uf, z, n, 1.0, h->stream);
   } else {
@@ -1041,7 +1045,7 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     const long n = top.n();
     hipStream_t st = h->stream;
     double *r = h->pr, *p = h->pp, *q = h->pq, *z = h->pz, *ro = h->pro;
-    // device scalars: [0] delta, [1] p.q, [2] r.r, [6] z.(r - r_old), [7] z.r, [8] sums
+    // device scalars: [0], [7] delta (alternating), [2] r.r, [8] sums
     double *sc = h->scal;
     launch_zero_boundary<double>(top.g, u, st);
     const double *fp = f;
@@ -1068,16 +1072,22 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     // r_old, q and scalars, never u or r) are queued before the host waits
     // for it, so the device does not idle during the round trip.  When the
     // test passes, queued work is discarded; u and r are final.
+    // No reduction has a launch of its own: the kernels that consume a dot
+    // product add its partial sums themselves (fixed order), and the host
+    // adds the r.r partials it copies for the stopping test.
+    const int npq = (int)residual_waves(top.g);
     auto q_and_pq = [&] {
-      residual<double>(h, L, p, nullptr, q, p, sc + 1);  // q = A p and p.q in one pass
+      residual<double>(h, L, p, nullptr, q, p);   // q = A p; p.q partials in h->partial
     };
     const bool mixed = h->precision != SEM_FP64;
+    double *delta = sc + 0, *delta_next = sc + 7;   // z.r, alternating between two slots
     auto next_direction = [&] {
       // the update below already wrote the cycle's inputs (prepared)
-      precondition(h, r, z, ns1, ns2, true, ro, mixed ? sc + 6 : nullptr);
-      if (!mixed) launch_dot2(z, r, ro, n, h->partial, sc + 6, st);  // z.(r - r_old), z.r
-      launch_cg_direction(sc + 6, sc + 0, p, z, ro, r, n, st);  // beta = z.(r-r_old)/delta
-      launch_copy_scalar(sc + 7, sc + 0, st);            // delta = z.r
+      precondition(h, r, z, ns1, ns2, true, ro, mixed ? h->part_d2 : nullptr);
+      if (!mixed) launch_dot2_partials(z, r, ro, n, h->part_d2, st);   // z.(r - r_old), z.r
+      // beta = z.(r - r_old) / delta; p = z + beta p; r_old = r; next delta = z.r
+      launch_cg_direction2(h->part_d2, delta, delta_next, p, z, ro, r, n, st);
+      std::swap(delta, delta_next);
     };
     int it = 0;
     bool done = r0 == 0.0;
@@ -1085,10 +1095,11 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     if (!done && imax > 0) q_and_pq();
     for (it = 1; it <= imax && !done; ++it) {
       // alpha = delta / p.q; also writes the next cycle's inputs
-      launch_cg_update(sc, u, p, r, q, n, h->partial, sc + 2, st, mixed ? top.ff : nullptr,
-                       mixed ? top.uf : nullptr, mixed ? nullptr : z);
-      double *slot = h->pin + (it & 1);
-      HIP_OK(hipMemcpyAsync(slot, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      const int nrr = launch_cg_update2(delta, h->partial, npq, u, p, r, q, n, h->part_rr, st,
+                                        mixed ? top.ff : nullptr, mixed ? top.uf : nullptr,
+                                        mixed ? nullptr : z);
+      double *slot = h->pin + (size_t)(it & 1) * kRedBlocks;
+      HIP_OK(hipMemcpyAsync(slot, h->part_rr, nrr * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_OK(hipEventRecord(h->nev[it & 1], st));
       // predicted ||r_k|| from the last two reductions
       const double pred = prev2 > 0.0 ? prev1 * (prev1 / prev2) : prev1;
@@ -1098,7 +1109,9 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
         q_and_pq();
       }
       HIP_OK(hipEventSynchronize(h->nev[it & 1]));
-      const double rn = std::sqrt(*slot);
+      double rr = 0.0;   // the partials in a fixed order
+      for (int b = 0; b < nrr; ++b) rr += slot[b];
+      const double rn = std::sqrt(rr);
       if (res_hist) res_hist[it] = rn;
       if (!std::isfinite(rn)) throw Fail{SEM_ENAN, "non-finite residual"};
       if (rn <= rtol * r0) {

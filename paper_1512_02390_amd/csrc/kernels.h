@@ -117,28 +117,35 @@ constexpr int kRedBlocks = 512;
 // res[0] = sum x*y
 void launch_dot(const double *x, const double *y, long n, double *partial, double *res,
                 hipStream_t s);
-// res[0] = sum z*(r - ro), res[1] = sum z*r  (Polak-Ribiere numerator, new delta)
-void launch_dot2(const double *z, const double *r, const double *ro, long n, double *partial,
-                 double *res, hipStream_t s);
 // res[0] = sum x
 void launch_sum(const double *x, long n, double *partial, double *res, hipStream_t s);
 // res = sum of partial[0 .. nb) (fixed order).
 void launch_reduce(const double *partial, int nb, double *res, hipStream_t s);
 // x -= res[0] / count on the unknowns of g (mean removal, periodic)
 void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s);
-// alpha = sc[0] / sc[1]; u += alpha p; r -= alpha q; res = sum r^2
-void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
-                      long n, double *partial, double *res, hipStream_t s, float *r32 = nullptr,
-                      float *z32 = nullptr, double *z64 = nullptr);
-// z = (double) z32; res[0] = z.(r - ro), res[1] = z.r.
-void launch_convert_dot2(const float *z32, double *z, const double *r, const double *ro, long n,
-                         double *partial, double *res, hipStream_t s);
-// beta = num[0] / den[0]; p = z + beta p; ro = r
-void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
-                         double *ro, const double *r, long n, hipStream_t s);
+// The MGCG loop's reductions without second-stage launches: the consumers add
+// the partial sums themselves (every block, fixed order).
+//   partial[b] = z.(r - ro), partial[kRedBlocks + b] = z.r  (b < red_blocks(n))
+void launch_dot2_partials(const double *z, const double *r, const double *ro, long n,
+                          double *partial, hipStream_t s);
+//   z = (double) z32, and the partials as above
+void launch_convert_dot2_partials(const float *z32, double *z, const double *r, const double *ro,
+                                  long n, double *partial, hipStream_t s);
+//   alpha = delta[0] / sum(pq_part[0 .. npq)); u += alpha p; r -= alpha q;
+//   rr_part[b] = partial sums of r.r (returned: their count).  When non-null
+//   it also writes the next V-cycle's inputs: r32 = (float) r, z32 = 0 or
+//   z64 = 0
+int launch_cg_update2(const double *delta, const double *pq_part, int npq, double *u,
+                      const double *p, double *r, const double *q, long n, double *rr_part,
+                      hipStream_t s, float *r32 = nullptr, float *z32 = nullptr,
+                      double *z64 = nullptr);
+//   beta = sum(slot 0) / delta[0]; p = z + beta p; ro = r; delta_new[0] = sum(slot 1)
+//   (d2_part as written by launch_dot2_partials for the same n)
+void launch_cg_direction2(const double *d2_part, const double *delta, double *delta_new,
+                          double *p, const double *z, double *ro, const double *r, long n,
+                          hipStream_t s);
 // y += alpha x
 void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s);
-void launch_copy_scalar(const double *src, double *dst, hipStream_t s);
 
 }  // namespace sem
 

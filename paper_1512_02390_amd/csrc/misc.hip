@@ -121,6 +121,19 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return red[0];
 }
 
+// Sum of part[0 .. n) in every thread of the block, in a fixed order (the
+// order of k_reduce_final): consumers of a reduction add its partial sums
+// themselves, each block redundantly, instead of waiting for a separate
+// one-block launch.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int n,
+                                               double *red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += RT) s += part[i];
+  const double t = block_sum(s, red);
+  __syncthreads();   // red is reused by the caller
+  return t;
+}
+
 __global__ void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y, long n,
                               double *__restrict__ partial) {
   __shared__ double red[RT];
@@ -171,30 +184,6 @@ __global__ void k_sub_mean(Grid g, double *__restrict__ x, const double *__restr
   if (idx < n) x[idx] -= sum[0] / (double)n;
 }
 
-// u += alpha p, r -= alpha q (alpha = sc[0] / sc[1]), partial sums of r.r;
-// optionally also prepares the next preconditioner call in the same pass:
-// r32 = (float) r, and zeros in z64 or z32 (the V-cycle's initial guess).
-__global__ void k_cg_update(const double *__restrict__ sc, double *__restrict__ u,
-                            const double *__restrict__ p, double *__restrict__ r,
-                            const double *__restrict__ q, long n, double *__restrict__ partial,
-                            float *__restrict__ r32, float *__restrict__ z32,
-                            double *__restrict__ z64) {
-  __shared__ double red[RT];
-  const double alpha = sc[0] / sc[1];
-  double s = 0.0;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
-    u[i] = fma(alpha, p[i], u[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
-    s = fma(ri, ri, s);
-    if (r32) r32[i] = (float)ri;
-    if (z32) z32[i] = 0.0f;
-    if (z64) z64[i] = 0.0;
-  }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
 // z = (double) z32 and the partial sums of z.(r - ro) and z.r (the inputs of
 // the Polak-Ribiere beta) in one pass.
 __global__ void k_convert_dot2(const float *__restrict__ z32, double *__restrict__ z,
@@ -217,24 +206,53 @@ __global__ void k_convert_dot2(const float *__restrict__ z32, double *__restrict
   }
 }
 
-__global__ void k_cg_direction(const double *__restrict__ num, const double *__restrict__ den,
-                               double *__restrict__ p, const double *__restrict__ z,
-                               double *__restrict__ ro, const double *__restrict__ r, long n) {
-  const double beta = num[0] / den[0];
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n) {
-    p[idx] = fma(beta, p[idx], z[idx]);
-    ro[idx] = r[idx];
-  }
-}
-
 __global__ void k_axpy(double alpha, const double *__restrict__ x, double *__restrict__ y, long n) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < n) y[idx] = fma(alpha, x[idx], y[idx]);
 }
 
-__global__ void k_copy_scalar(const double *__restrict__ src, double *__restrict__ dst) {
-  if (threadIdx.x == 0) dst[0] = src[0];
+// MGCG update with the reductions folded in: alpha = delta / (p.q), p.q the
+// sum of the npq partials of the A p residual kernel; r.r partials (one per
+// block) for the host; optionally the next V-cycle's inputs (r in FP32, a
+// zero initial guess in FP32 or FP64).
+__global__ void k_cg_update2(const double *__restrict__ delta, const double *__restrict__ pq_part,
+                             int npq, double *__restrict__ u, const double *__restrict__ p,
+                             double *__restrict__ r, const double *__restrict__ q, long n,
+                             double *__restrict__ rr_part, float *__restrict__ r32,
+                             float *__restrict__ z32, double *__restrict__ z64) {
+  __shared__ double red[RT];
+  const double alpha = delta[0] / sum_partials(pq_part, npq, red);
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+    u[i] = fma(alpha, p[i], u[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    s = fma(ri, ri, s);
+    if (r32) r32[i] = (float)ri;
+    if (z32) z32[i] = 0.0f;
+    if (z64) z64[i] = 0.0;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
+}
+
+// Polak-Ribiere direction with the reductions folded in: num = z.(r - ro) and
+// delta_new = z.r are the sums of the nb partials in d2_part (slots 0 and 1,
+// kRedBlocks apart); beta = num / delta; p = z + beta p; ro = r; block 0
+// stores delta_new (a different slot than delta: other blocks still read it).
+__global__ void k_cg_direction2(const double *__restrict__ d2_part, int nb,
+                                const double *__restrict__ delta, double *__restrict__ delta_new,
+                                double *__restrict__ p, const double *__restrict__ z,
+                                double *__restrict__ ro, const double *__restrict__ r, long n) {
+  __shared__ double red[RT];
+  const double num = sum_partials(d2_part, nb, red);
+  const double dn = sum_partials(d2_part + kRedBlocks, nb, red);
+  const double beta = num / delta[0];
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+    p[i] = fma(beta, p[i], z[i]);
+    ro[i] = r[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) delta_new[0] = dn;
 }
 
 int red_blocks(long n) {
@@ -302,13 +320,6 @@ void launch_dot(const double *x, const double *y, long n, double *partial, doubl
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
 }
 
-void launch_dot2(const double *z, const double *r, const double *ro, long n, double *partial,
-                 double *res, hipStream_t s) {
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_dot2_partial, dim3(nb), dim3(RT), 0, s, z, r, ro, n, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(2), dim3(RT), 0, s, partial, nb, res);
-}
-
 void launch_sum(const double *x, long n, double *partial, double *res, hipStream_t s) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(RT), 0, s, x, n, partial);
@@ -320,34 +331,37 @@ void launch_sub_mean(const Grid &g, double *x, const double *sum, hipStream_t s)
   hipLaunchKernelGGL(k_sub_mean, dim3(ceil_div(n, 256)), dim3(256), 0, s, g, x, sum);
 }
 
-void launch_cg_update(const double *sc, double *u, const double *p, double *r, const double *q,
-                      long n, double *partial, double *res, hipStream_t s, float *r32,
-                      float *z32, double *z64) {
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(RT), 0, s, sc, u, p, r, q, n, partial, r32, z32,
-                     z64);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
+void launch_dot2_partials(const double *z, const double *r, const double *ro, long n,
+                          double *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2_partial, dim3(red_blocks(n)), dim3(RT), 0, s, z, r, ro, n, partial);
 }
 
-void launch_convert_dot2(const float *z32, double *z, const double *r, const double *ro, long n,
-                         double *partial, double *res, hipStream_t s) {
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_convert_dot2, dim3(nb), dim3(RT), 0, s, z32, z, r, ro, n, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(2), dim3(RT), 0, s, partial, nb, res);
+void launch_convert_dot2_partials(const float *z32, double *z, const double *r, const double *ro,
+                                  long n, double *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_dot2, dim3(red_blocks(n)), dim3(RT), 0, s, z32, z, r, ro, n,
+                     partial);
 }
 
-void launch_cg_direction(const double *num, const double *den, double *p, const double *z,
-                         double *ro, const double *r, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(ceil_div(n, 256)), dim3(256), 0, s, num, den, p, z, ro,
-                     r, n);
+int launch_cg_update2(const double *delta, const double *pq_part, int npq, double *u,
+                      const double *p, double *r, const double *q, long n, double *rr_part,
+                      hipStream_t s, float *r32, float *z32, double *z64) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb), dim3(RT), 0, s, delta, pq_part, npq, u, p, r, q, n,
+                     rr_part, r32, z32, z64);
+  return nb;
+}
+
+void launch_cg_direction2(const double *d2_part, const double *delta, double *delta_new,
+                          double *p, const double *z, double *ro, const double *r, long n,
+                          hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_cg_direction2, dim3(nb), dim3(RT), 0, s, d2_part, nb, delta, delta_new, p,
+                     z, ro, r, n);
 }
 
 void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy, dim3(ceil_div(n, 256)), dim3(256), 0, s, alpha, x, y, n);
 }
 
-void launch_copy_scalar(const double *src, double *dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, s, src, dst);
-}
 
 }  // namespace sem
