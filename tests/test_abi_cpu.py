@@ -72,3 +72,23 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode != 0
     assert "one GPU" in res.stderr
+
+
+def test_precision_enum_matches_binding():
+    text = open(HEADER).read()
+    body = re.search(r"typedef enum \{([^}]*)\} sem_precision;", text).group(1)
+    vals = {k: int(v) for k, v in re.findall(r"(SEM_\w+)\s*=\s*(\d+)", body)}
+    from paper_1512_02390_amd import sem
+    assert vals == {"SEM_FP64": sem.FP64, "SEM_MIXED_FP32": sem.MIXED_FP32,
+                    "SEM_MIXED_BF16": sem.MIXED_BF16, "SEM_MIXED_FP16": sem.MIXED_FP16}
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_setup_rejects_unknown_precision_without_device():
+    lib = ctypes.CDLL(LIB)
+    lib.sem_setup.restype = ctypes.c_int32
+    h = ctypes.c_void_p(1)
+    for prec in (-1, 4):
+        # checked before the mesh is read or the device touched
+        assert lib.sem_setup(None, 4, None, None, None, prec, None, ctypes.byref(h)) == -1
+        assert h.value is None
