@@ -160,7 +160,8 @@ sem_status sem_vcycle(sem_handle h, double *u, const double *f, const int32_t *n
  * queued after the final test (which touches only internal vectors) may
  * still be running on the stream.  iters: iterations done;
  * res_hist: optional host array of imax+1 residual norms.  Returns
- * SEM_ENOCONV when imax is reached (u holds the last iterate). */
+ * SEM_ENOCONV when imax is reached (u holds the last iterate).  A zero
+ * initial residual returns at once: iters = 0, u unchanged. */
 sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax, double rtol,
                          const int32_t *ns1, const int32_t *ns2, int32_t *iters,
                          double *res_hist);

@@ -1063,6 +1063,10 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     const double r0 = std::sqrt(read_scalar(h, sc + 2));
     if (!std::isfinite(r0)) throw Fail{SEM_ENAN, "non-finite initial residual"};
     if (res_hist) res_hist[0] = r0;
+    if (r0 == 0.0) {   // u is already the solution: no iteration (and no 0/0 in alpha)
+      if (iters) *iters = 0;
+      return;
+    }
     precondition(h, r, p, ns1, ns2);
     launch_dot(p, r, n, h->partial, sc + 0, st);
     // The stopping test of iteration k needs ||r_k|| on the host.  Its copy
@@ -1090,7 +1094,7 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
       std::swap(delta, delta_next);
     };
     int it = 0;
-    bool done = r0 == 0.0;
+    bool done = false;
     double prev1 = r0, prev2 = 0.0;   // the last two residual norms
     if (!done && imax > 0) q_and_pq();
     for (it = 1; it <= imax && !done; ++it) {

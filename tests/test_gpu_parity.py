@@ -139,3 +139,29 @@ def test_pcg(pair):
         Ug = Ug - Ug.mean()
         Uref = Uref - Uref.mean()
     assert rel_err(Ug, Uref) < 1e-9
+
+
+def test_pcg_degenerate_cases():
+    """Zero initial residual: no iteration, u unchanged (the algorithm's
+    alpha would be 0/0).  imax = 0: not converged, u unchanged, the history
+    holds the oracle's ||r_0||."""
+    case = next(c for c in CASES if c.name == "dir_p4_no1")
+    mg, NU = build_oracle(case)
+    gpu = build_gpu(case, NU)
+    try:
+        sp = mg.spaces[-1]
+        zero = np.zeros(sp.shape)
+        u = _dev(zero)
+        it, hist, ok = gpu.pcg_solve(u, _dev(zero), 20, 1e-10)
+        assert ok and it == 0 and hist[0] == 0.0
+        assert np.all(_host(u) == 0.0)
+        U0 = W.random_guess(sp.shape, case.bc, 95)
+        F = W.random_nodal(sp.shape, case.bc, 96)
+        u = _dev(U0)
+        it, hist, ok = gpu.pcg_solve(u, _dev(F), 0, 1e-10)
+        assert not ok and it == 0
+        r0 = np.linalg.norm(mg.residual(mg.L, U0, F)[sp.mask])
+        assert abs(hist[0] - r0) <= 1e-12 * r0
+        assert np.array_equal(_host(u), np.where(sp.mask, U0, 0.0)) or np.array_equal(_host(u), U0)
+    finally:
+        gpu.close()
