@@ -38,7 +38,7 @@ typedef enum {
   SEM_EHIP = -4,     /* a HIP runtime call failed                          */
   SEM_ENOCONV = -5,  /* pcg_solve reached imax; u holds the last iterate   */
   SEM_ENAN = -6,     /* non-finite residual encountered                    */
-  SEM_EUNSUP = -7    /* supported by the method but not by this build
+  SEM_EUNSUP = -7    /* supported by the method but not by this library
                         (tile size, coarse grid too large for nu != 1)     */
 } sem_status;
 
@@ -200,7 +200,7 @@ sem_status sem_elem_features(sem_handle h, float *feat);
 /* Multilayer perceptron d_in -> width -> width -> d_out with tanh hidden
  * layers and logistic outputs, trained on the device with the loss
  * 1/(2n) sum_s sum_o (y_so - t_so)^2 and Adam (beta1 0.9, beta2 0.999,
- * eps 1e-8, bias-corrected).  This build supports width = 64, d_in <= 16,
+ * eps 1e-8, bias-corrected).  The library supports width = 64, d_in <= 16,
  * d_out <= 4 (SEM_EUNSUP otherwise).  Parameters are one flat FP32 array:
  * W1 (width x d_in, row-major), b1, W2 (width x width), b2, W3
  * (d_out x width), b3. */

@@ -1196,7 +1196,7 @@ const char *sem_strerror(sem_status s) {
     case SEM_EHIP: return "HIP runtime error";
     case SEM_ENOCONV: return "no convergence within imax";
     case SEM_ENAN: return "non-finite value";
-    case SEM_EUNSUP: return "unsupported by this build";
+    case SEM_EUNSUP: return "unsupported by this library";
   }
   return "unknown status";
 }
