@@ -92,3 +92,40 @@ def test_setup_rejects_unknown_precision_without_device():
         # checked before the mesh is read or the device touched
         assert lib.sem_setup(None, 4, None, None, None, prec, None, ctypes.byref(h)) == -1
         assert h.value is None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_setup_validation_without_device():
+    """Argument checks of sem_setup that precede every device call: bad
+    order, element counts, boundary condition, periodic size, overlap,
+    weight function, width scales (EINVAL) and non-increasing breaks (EDOM)."""
+    import numpy as np
+    from paper_1512_02390_amd import sem as S
+    C = ctypes
+    lib = ctypes.CDLL(LIB)
+    lib.sem_setup.restype = C.c_int32
+
+    def setup(nx=3, ny=3, p=4, bc=0, rule=1, n_o=1, wf=5, xb=None, yb=None, alpha=None):
+        xb = np.linspace(0.0, 1.0, nx + 1) if xb is None else np.asarray(xb, dtype=np.float64)
+        yb = np.linspace(0.0, 1.0, ny + 1) if yb is None else np.asarray(yb, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        mesh = S._Mesh(nx, ny, xb.ctypes.data_as(dp), yb.ctypes.data_as(dp), bc)
+        ov = S._Overlap(rule, n_o, None)
+        ax = None if alpha is None else np.asarray(alpha, dtype=np.float64)
+        w = S._Weights(wf, None if ax is None else ax.ctypes.data_as(dp), None)
+        h = C.c_void_p(1)
+        st = lib.sem_setup(C.byref(mesh), p, C.byref(ov), C.byref(w), None, 0, None, C.byref(h))
+        assert h.value is None
+        return st
+
+    EINVAL, EDOM = -1, -2
+    assert setup(p=0) == EINVAL
+    assert setup(nx=0) == EINVAL
+    assert setup(bc=7) == EINVAL
+    assert setup(bc=1, nx=2) == EINVAL            # periodic needs 3 elements
+    assert setup(rule=0, n_o=-1) == EINVAL
+    assert setup(wf=4) == EINVAL                  # even kappa
+    assert setup(alpha=[1.0, 0.0, 1.0, 1.0]) == EINVAL
+    assert setup(alpha=[1.0, 1.5, 1.0, 1.0]) == EINVAL
+    assert setup(xb=[0.0, 0.5, 0.5, 1.0]) == EDOM
+    assert setup(yb=[0.0, 0.7, 0.4, 1.0]) == EDOM
