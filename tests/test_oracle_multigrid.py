@@ -230,3 +230,21 @@ def test_metrics_against_tables():
         assert n10(r + 0.005) <= n <= n10(r - 0.005)
         assert omega_k_tables(r, p, n_o, ccg=2.0) == pytest.approx(om, rel=0.005 / r + 0.015)
     assert rbar([1.0, 1e-2, 1e-4]) == pytest.approx(2.0)
+
+
+def test_coarse_level_nu_is_the_interpolated_field():
+    """Each coarser level's nu is the element-local interpolation of the
+    finest nodal nu (reading C-L4): for a nu of degree 2 in each element that
+    interpolation is exact on every level of order >= 2, and on the p = 1
+    level it is the bilinear interpolant at the element corners (which are
+    finest-level nodes, so the values there are exact too)."""
+    nu = lambda x, y: 1.0 + 0.5 * x + 0.25 * y * y
+    xb = np.array([0.0, 0.3, 0.6, 1.0])
+    yb = W.uniform_breaks(3, 1.0)
+    top = Space(xb, yb, 8, DIRICHLET)
+    NU = W.nodal(nu, top.x(), top.y())
+    mg = Multigrid(xb, yb, 8, DIRICHLET, 1, 1, 5, NU=NU)
+    for l, s in enumerate(mg.spaces):
+        ref = W.nodal(nu, s.x(), s.y())
+        err = np.abs(mg.NU[l] - ref).max()
+        assert err < 1e-12, (l, s.p, err)
