@@ -28,7 +28,7 @@ import scipy.sparse.linalg as spla
 
 from .discretization import PERIODIC, Space, element_mean
 from .gll import gll, lagrange_matrix
-from .schwarz import SchwarzLevel
+from .schwarz import ElementwiseSchwarzLevel, SchwarzLevel
 
 OVERLAP_FIXED, OVERLAP_CEIL8, OVERLAP_FLOOR8, OVERLAP_CEIL2 = 0, 1, 2, 3
 
@@ -52,6 +52,18 @@ def level_overlap(rule: int, n_o: int, p_l: int) -> int:
     else:
         raise ValueError(rule)
     return max(0, min(v, p_l - 1))
+
+
+MAX_TILE = 48   # widest subdomain p_l + 1 + 2 n_o the per-element rule produces
+
+
+def element_overlap(rho: float, p_l: int) -> int:
+    """Per-element overlap on level l from an overlap ratio rho (learned
+    parameters): ceil(rho p_l) clamped to [1, p_l - 1] and to a subdomain
+    width p_l + 1 + 2 n_o of at most MAX_TILE nodes."""
+    v = math.ceil(rho * p_l - 1e-12)
+    v = min(max(v, 1), p_l - 1, (MAX_TILE - p_l - 1) // 2)
+    return max(v, 0)
 
 
 def prolongation_1d(axis_c, axis_f) -> np.ndarray:
@@ -79,8 +91,12 @@ def interpolate_nodal(space_from: Space, space_to: Space, V) -> np.ndarray:
 
 class Multigrid:
     def __init__(self, xb, yb, p: int, bc: int, overlap_rule: int = OVERLAP_FIXED,
-                 n_o: int = 1, wf: int = 5, NU=None, alpha_x=None, alpha_y=None, overlaps=None):
-        """overlaps: optional explicit n_o per level (index 0 unused)."""
+                 n_o: int = 1, wf: int = 5, NU=None, alpha_x=None, alpha_y=None, overlaps=None,
+                 elem_params=None):
+        """overlaps: optional explicit n_o per level (index 0 unused).
+        elem_params: optional (alpha_e, rho_e), two (ny, nx) arrays of per-
+        element width scales and overlap ratios; every level l > 0 then uses
+        ElementwiseSchwarzLevel with n_o,e = element_overlap(rho_e, p_l)."""
         self.orders = level_orders(p)
         self.L = len(self.orders) - 1
         self.bc = bc
@@ -100,9 +116,21 @@ class Multigrid:
             top = self.spaces[-1]
             self.NU = [interpolate_nodal(top, s, NU) for s in self.spaces[:-1]] + [np.array(NU)]
             self.nubar = element_mean(top, NU)
-        self.schwarz = [None] + [
-            SchwarzLevel(self.spaces[l], self.overlaps[l], wf, alpha_x, alpha_y)
-            for l in range(1, self.L + 1)]
+        if elem_params is not None:
+            alpha_e = np.asarray(elem_params[0], dtype=np.float64)
+            rho_e = np.asarray(elem_params[1], dtype=np.float64)
+            self.elem_no = [None]
+            self.schwarz = [None]
+            for l in range(1, self.L + 1):
+                q = self.orders[l]
+                no = np.vectorize(lambda r: element_overlap(r, q))(rho_e).astype(int)
+                self.elem_no.append(no)
+                self.overlaps[l] = int(no.max())
+                self.schwarz.append(ElementwiseSchwarzLevel(self.spaces[l], no, alpha_e, wf))
+        else:
+            self.schwarz = [None] + [
+                SchwarzLevel(self.spaces[l], self.overlaps[l], wf, alpha_x, alpha_y)
+                for l in range(1, self.L + 1)]
         self._coarse_setup()
 
     # -- operators ------------------------------------------------------------

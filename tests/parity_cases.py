@@ -26,6 +26,7 @@ class Case:
     wf: int = 5
     varnu: bool = False
     overlaps: tuple | None = None   # explicit n_o per level (entry 0 unused)
+    alpha_seed: int | None = None   # random width scales per grid line in [0.2, 1]
 
     def breaks(self):
         if self.stretched:
@@ -34,6 +35,18 @@ class Case:
             xb = W.uniform_breaks(self.nx, 1.3)
         yb = W.uniform_breaks(self.ny, 1.0)
         return xb, yb
+
+    def alphas(self):
+        """(alpha_x, alpha_y) per grid line, or (None, None) for the paper's
+        weights.  Periodic: the last line is the first one, so it repeats it."""
+        if self.alpha_seed is None:
+            return None, None
+        g = W.rng(self.alpha_seed)
+        ax = g.uniform(0.2, 1.0, self.nx + 1)
+        ay = g.uniform(0.2, 1.0, self.ny + 1)
+        if self.bc == W.BC_PERIODIC:
+            ax[-1], ay[-1] = ax[0], ay[0]
+        return ax, ay
 
 
 CASES = [
@@ -53,6 +66,14 @@ CASES = [
     Case("dir_p12_ceil2_varnu_stretch", 4, 3, 12, D, stretched=True, rule=CEIL2, varnu=True),
     Case("dir_p32_levels_varnu_stretch", 2, 2, 32, D, stretched=True, varnu=True,
          overlaps=(0, 1, 1, 2, 4, 7)),
+    # width scales alpha != 1 per grid line (the hook of the learned parameters)
+    Case("dir_p8_no2_alpha_stretch", 5, 4, 8, D, stretched=True, n_o=2, alpha_seed=11),
+    Case("per_p6_no2_alpha", 4, 5, 6, P, n_o=2, alpha_seed=12),
+    Case("dir_p12_ceil8_alpha_varnu", 3, 4, 12, D, stretched=True, rule=CEIL8, varnu=True,
+         alpha_seed=13),
+    # the seventh-order weight function of Table 1
+    Case("per_p4_no1_septic", 4, 3, 4, P, wf=7),
+    Case("dir_p16_ceil8_septic", 3, 2, 16, D, rule=CEIL8, wf=7),
 ]
 
 
@@ -69,15 +90,17 @@ def build_oracle(case: Case):
     if nu is not None:
         top = Space(xb, yb, case.p, case.bc)
         NU = W.nodal(nu.nu, top.x(), top.y())
+    ax, ay = case.alphas()
     return Multigrid(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, NU=NU,
-                     overlaps=case.overlaps), NU
+                     alpha_x=ax, alpha_y=ay, overlaps=case.overlaps), NU
 
 
 def build_gpu(case: Case, NU=None, precision=0):
     from paper_1512_02390_amd.sem import Solver
     xb, yb = case.breaks()
+    ax, ay = case.alphas()
     return Solver(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, nu=NU,
-                  precision=precision, overlaps=case.overlaps)
+                  precision=precision, overlaps=case.overlaps, alpha_x=ax, alpha_y=ay)
 
 
 def rel_err(a, b) -> float:

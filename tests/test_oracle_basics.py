@@ -118,6 +118,36 @@ def test_variable_nu_operator():
     assert np.allclose(element_mean(sp, 3.0 * np.ones(sp.shape)), 3.0)
 
 
+@pytest.mark.parametrize("p", [3, 4, 7])
+def test_element_mean_of_polynomial_field_is_exact(p):
+    """nu_bar_e (Section 4) is the mean of nu over the element.  For a field
+    that is a polynomial of degree <= 2p - 1 in each variable the GLL rule is
+    exact, so on a stretched mesh nu_bar_e equals the closed-form mean
+    (1 / |e|) int_e nu.  A plain average of the nodal values fails this."""
+    xb = W.geometric_breaks(4, 0.2, 3.0)
+    yb = np.array([0.0, 0.15, 0.5, 1.3])
+    sp = Space(xb, yb, p, DIRICHLET)
+
+    def nu(x, y):
+        return 1.0 + x ** 2 * y + 3.0 * y ** 3 + 0.5 * x ** 5 * y ** 2
+
+    def mean_pow(a, b, k):
+        return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+
+    NU = W.nodal(nu, sp.x(), sp.y())
+    got = element_mean(sp, NU)
+    for ey in range(len(yb) - 1):
+        for ex in range(len(xb) - 1):
+            a, b, c, d = xb[ex], xb[ex + 1], yb[ey], yb[ey + 1]
+            exact = (1.0 + mean_pow(a, b, 2) * mean_pow(c, d, 1) + 3.0 * mean_pow(c, d, 3)
+                     + 0.5 * mean_pow(a, b, 5) * mean_pow(c, d, 2))
+            assert abs(got[ey, ex] - exact) < 1e-13 * exact
+    # the unweighted nodal average is a different number on these elements
+    gy = [sp.ay.node_index(1, b) for b in range(p + 1)]
+    gx = [sp.ax.node_index(2, a) for a in range(p + 1)]
+    assert abs(NU[np.ix_(gy, gx)].mean() - got[1, 2]) > 1e-3 * got[1, 2]
+
+
 def _solve_dirichlet(n, p):
     xb = W.uniform_breaks(n, 1.0)
     sp = Space(xb, xb, p, DIRICHLET)

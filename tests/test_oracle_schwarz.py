@@ -104,19 +104,38 @@ def test_partition_of_unity_with_width_scales():
         assert np.allclose(S[lev.space.mask], 1.0, atol=1e-14)
 
 
-@pytest.mark.parametrize("p,n_o", [(4, 1), (6, 1), (8, 1), (8, 2), (16, 2), (3, 0)])
+@pytest.mark.parametrize("p,n_o", [(4, 1), (6, 1), (6, 2), (8, 1), (8, 2), (8, 3), (16, 2), (3, 0)])
 def test_arithmetic_weights_match_formula_on_open_interval(p, n_o):
-    """W = R_s C^+ R_s^T (counting) equals the weight function with phi^ = 0
-    whenever the node on |arg| = 1 is not an unknown of the subdomain."""
+    """W = R_s C^+ R_s^T (inverse counting, Section 3.1) equals the weight
+    function with phi^ = 0 on the open interval (-1, 1) (w_a of Table 1) at
+    every node of the subdomain whose argument (xi +- 1)/delta_o is not +-1.
+    The node at local index n_o + 1 from each interface sits exactly on
+    |arg| = 1 by the definition of delta_o; there phi = sgn(arg) = +-1 and the
+    formula gives 1, which must be the inverse count (one owner)."""
     xb = W.uniform_breaks(4, 1.0)
     lev = SchwarzLevel(Space(xb, xb, p, PERIODIC), n_o, WF_ARITH)
     s = lev.sx[1]
     d = s.delta_left
-    if d <= 1.0 and np.min(np.abs(np.abs(s.xi_ext) - 1 - d)) > 1e-9 \
-            and np.min(np.abs(np.abs(s.xi_ext) - (1 - d))) > 1e-9:
-        w_formula = weight(WF_ARITH, s.xi_ext, d, d)
-        w_count = lev.subdomain_weights(1, 1)
-        assert np.allclose(np.outer(w_formula, w_formula), w_count, atol=1e-15)
+    assert d <= 1.0 + 1e-12          # the formula route only holds for delta_o <= 1
+    al = (s.xi_ext + 1.0) / d
+    ar = (s.xi_ext - 1.0) / d
+    on_edge = (np.abs(np.abs(al) - 1.0) < 1e-9) | (np.abs(np.abs(ar) - 1.0) < 1e-9)
+    off = ~on_edge
+    # the edge nodes are exactly the two nodes n_o + 1 away from the interfaces
+    # (one node, the centre, when delta_o = 1)
+    assert 1 <= on_edge.sum() <= 2
+    assert off.sum() >= s.m - 2
+    w_formula = weight(WF_ARITH, s.xi_ext, d, d)
+    w_count = lev.subdomain_weights(1, 1)
+    # the 2-D counting weights factor into 1-D ones on a uniform periodic mesh
+    w1 = w_count[s.m // 2, :]
+    assert np.allclose(np.outer(w1, w1), w_count, atol=1e-15)
+    assert np.allclose(w_formula[off], w1[off], atol=1e-15)
+    # open-interval value at |arg| = 1: phi = sgn, so w = 1 (single owner)
+    assert np.allclose(w1[on_edge], 1.0, atol=1e-15)
+    # the overlap zone itself: counts of two give 1/2 (interface and n_o
+    # layers on each side)
+    assert np.isclose(w1[n_o], 0.5) and np.isclose(w1[0], 0.5)
 
 
 def _tiny_cases():
@@ -170,3 +189,133 @@ def test_nu_bar_scaling_of_corrections():
     c1 = lev.corrections(R)
     c2 = lev.corrections(R, 4.0 * np.ones((3, 3)))
     assert np.allclose(c2, c1 / 4.0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Per-element parameters with Shepard normalisation (learned-parameter
+# extension): u += D^{-1} sum_s R_s^T W_s du_s, D = sum_s R_s^T W_s R_s.
+# ---------------------------------------------------------------------------
+from oracle.schwarz import ElementwiseSchwarzLevel  # noqa: E402
+
+
+@pytest.mark.parametrize("bc,wf,p,n_o", [(DIRICHLET, 5, 6, 2), (PERIODIC, 3, 5, 1),
+                                         (DIRICHLET, WF_TOPHAT, 4, 1), (PERIODIC, WF_ARITH, 6, 2),
+                                         (DIRICHLET, 7, 8, 3)])
+def test_elementwise_uniform_parameters_reduce_to_paper(bc, wf, p, n_o):
+    """Equal parameters on every element: D = 1 (the weights of Section 3.1
+    are a partition of unity) and the update is the paper's."""
+    xb = W.geometric_breaks(4, 0.25, 3.0)
+    yb = W.uniform_breaks(3, 1.0)
+    sp = Space(xb, yb, p, bc)
+    ref = SchwarzLevel(sp, n_o, wf)
+    el = ElementwiseSchwarzLevel(sp, np.full((3, 4), n_o), np.ones((3, 4)), wf)
+    if wf != WF_ARITH:
+        assert np.abs(el.D[sp.mask] - 1.0).max() < 1e-14
+    R = W.random_nodal(sp.shape, bc, 5)
+    a, b = ref.corrections(R), el.corrections(R)
+    assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
+
+
+def _brute_windows(n, p, bc, no_per_elem):
+    """Global 1-D node indices of every element's window [e p - n_o, (e+1) p + n_o]
+    (periodic: wrapped; Dirichlet: the unknowns 1 .. n p - 1 only)."""
+    N = n * p if bc == PERIODIC else n * p + 1
+    out = []
+    for e in range(n):
+        idx = []
+        for g in range(e * p - no_per_elem[e], (e + 1) * p + no_per_elem[e] + 1):
+            if bc == PERIODIC:
+                idx.append(g % N)
+            elif 1 <= g <= N - 2:
+                idx.append(g)
+        out.append(idx)
+    return out
+
+
+@pytest.mark.parametrize("bc", [DIRICHLET, PERIODIC])
+def test_elementwise_arithmetic_normaliser_is_counting(bc):
+    """With unit weights D counts how many per-element windows hold each
+    unknown, so D^{-1} W_s = R_s C^+ R_s^T (the arithmetic mean of Table 1)
+    for any per-element overlaps.  Counted here by brute force over index
+    windows written out from Section 3.1's definition."""
+    n, p = 5, 4
+    xb = W.uniform_breaks(n, 1.0)
+    yb = W.uniform_breaks(4, 1.0)
+    sp = Space(xb, yb, p, bc)
+    g = W.rng(31)
+    no = g.integers(0, p, size=(4, n))
+    el = ElementwiseSchwarzLevel(sp, no, np.ones((4, n)), WF_ARITH)
+    C = np.zeros(sp.shape)
+    for ey in range(4):
+        for ex in range(n):
+            wy = _brute_windows(4, p, bc, no[:, ex])[ey]
+            wx = _brute_windows(n, p, bc, no[ey, :])[ex]
+            for i in wy:
+                for j in wx:
+                    C[i, j] += 1
+    assert np.array_equal(el.D[sp.mask], C[sp.mask])
+
+
+@pytest.mark.parametrize("bc,wf", [(DIRICHLET, 5), (PERIODIC, 5), (DIRICHLET, 3), (PERIODIC, WF_TOPHAT)])
+def test_elementwise_update_matches_dense_definition(bc, wf):
+    """Brute force on a tiny mesh: the normalised update built from the dense
+    global matrix, explicit 0/1 restrictions of each element's window and the
+    weight function at the window's extended coordinates, with random
+    per-element overlaps and width scales."""
+    nx, ny, p = 3, 3, 4
+    xb = W.geometric_breaks(nx, 0.3, 2.0)
+    yb = W.uniform_breaks(ny, 1.0)
+    sp = Space(xb, yb, p, bc)
+    g = W.rng(32)
+    no = g.integers(1, p, size=(ny, nx))
+    al = g.uniform(0.3, 1.0, size=(ny, nx))
+    el = ElementwiseSchwarzLevel(sp, no, al, wf)
+    A = sp.dense_B(np.ones(sp.shape))
+    num = -np.ones(sp.shape, dtype=int)
+    num[sp.mask] = np.arange(sp.mask.sum())
+    xi, _ = gll(p)
+    R = W.random_nodal(sp.shape, bc, 33)
+    r = R[sp.mask]
+    acc = np.zeros(len(r))
+    dsum = np.zeros(len(r))
+
+    def ext_coords(e, n, n_o):
+        out = []
+        for t in range(-n_o, p + n_o + 1):
+            out.append(xi[p + t] - 2.0 if t < 0 else (xi[t - p] + 2.0 if t > p else xi[t]))
+        return np.array(out)
+
+    for ey in range(ny):
+        for ex in range(nx):
+            n_o = int(no[ey, ex])
+            d = al[ey, ex] * (xi[n_o + 1] + 1.0)
+            wins, ws = [], []
+            for (e, n) in ((ey, ny), (ex, nx)):
+                full = list(range(e * p - n_o, (e + 1) * p + n_o + 1))
+                xe = ext_coords(e, n, n_o)
+                N = n * p if bc == PERIODIC else n * p + 1
+                keep = [k for k, gi in enumerate(full) if bc == PERIODIC or 1 <= gi <= N - 2]
+                wins.append([full[k] % N for k in keep])
+                sat_l = bc == DIRICHLET and e == 0
+                sat_r = bc == DIRICHLET and e == n - 1
+                ws.append(weight(wf, xe[keep], d, d, sat_l, sat_r))
+            ids = num[np.ix_(wins[0], wins[1])].ravel()
+            Rs = np.zeros((len(ids), len(r)))
+            Rs[np.arange(len(ids)), ids] = 1.0
+            Ws = np.outer(ws[0], ws[1]).ravel()
+            dl = np.linalg.solve(Rs @ A @ Rs.T, Rs @ r)
+            acc += Rs.T @ (Ws * dl)
+            dsum += Rs.T @ Ws
+    ref = acc / dsum
+    got = el.corrections(R)[sp.mask]
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_elementwise_single_element_is_exact_solve():
+    """One Dirichlet element: D^{-1} W = 1 on the whole domain for any width
+    scale, so one sweep solves the system."""
+    sp = Space([0.0, 1.0], [0.0, 2.0], 6, DIRICHLET)
+    el = ElementwiseSchwarzLevel(sp, np.array([[3]]), np.array([[0.4]]), 5)
+    F = W.random_nodal(sp.shape, DIRICHLET, 3)
+    U = el.smooth(np.zeros(sp.shape), F, 1)
+    assert np.abs(F - sp.apply_A(U))[sp.mask].max() < 1e-12 * np.abs(F).max()
