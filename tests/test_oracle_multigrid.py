@@ -248,3 +248,42 @@ def test_coarse_level_nu_is_the_interpolated_field():
         ref = W.nodal(nu, s.x(), s.y())
         err = np.abs(mg.NU[l] - ref).max()
         assert err < 1e-12, (l, s.p, err)
+
+
+def test_random_field_needs_resolved_correlation_length():
+    """Why the variable-diffusion workloads use correlation length 1.0 rather
+    than 0.1: the local solves scale by one element mean nu_bar per subdomain
+    (Section 4), which the paper notes works when the mesh resolves nu.  On the
+    6 x 6 widest elements of the 32 x 32 stretched workload mesh (widths up to
+    0.5, aspect ratio up to 16), p = 12, MGCG(1,1) with ceil(p_l/8) overlaps
+    and quintic weights converges with length 1.0 and breaks down (non-finite
+    iterates) or stagnates with length 0.1, where nu varies by orders of
+    magnitude inside one element."""
+    import warnings
+    cfg = W.config("c4")
+    xb, yb = cfg.xb[26:], cfg.yb[:7]
+    out = {}
+    for ell in (1.0, 0.1):
+        nu = W.GaussianFieldNu(ell=ell)
+        top = Space(xb, yb, 12, DIRICHLET)
+        NU = W.nodal(nu.nu, top.x(), top.y())
+        mg = Multigrid(xb, yb, 12, DIRICHLET, 1, 0, 5, NU=NU)
+        F = top.mass(W.random_nodal(top.shape, DIRICHLET, W.SEED_RHS))
+        U0 = W.random_guess(top.shape, DIRICHLET, W.SEED_U0)
+        ns1, ns2 = smoothing_schedule(mg.L, "mg11")
+        try:
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                _, hist, it = mgcg(mg, U0, F, 30, 1e-10, ns1, ns2)
+            out[ell] = (it, hist[-1] / hist[0])
+        except (ValueError, FloatingPointError, np.linalg.LinAlgError):
+            out[ell] = (None, np.inf)     # breakdown: non-finite iterate
+        # spread of nu inside the elements
+        spread = max(np.ptp(np.log(NU[np.ix_(gy, gx)]))
+                     for gy, gx in (top.element_nodes(ey, ex) for ey in range(6) for ex in range(6)))
+        out[ell] += (spread,)
+    it1, red1, spread1 = out[1.0]
+    assert it1 is not None and red1 <= 1e-10 and it1 <= 25, out
+    _, red01, spread01 = out[0.1]
+    assert not (red01 <= 1e-3), out          # no convergence, or breakdown
+    assert spread01 > 3.0 * spread1, out

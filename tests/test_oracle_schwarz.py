@@ -319,3 +319,23 @@ def test_elementwise_single_element_is_exact_solve():
     F = W.random_nodal(sp.shape, DIRICHLET, 3)
     U = el.smooth(np.zeros(sp.shape), F, 1)
     assert np.abs(F - sp.apply_A(U))[sp.mask].max() < 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_zero_overlap_weight_functions_coincide(p):
+    """With n_o = 0 (Table 3's rule floor(p_l/8) below p_l = 8) the subdomain
+    holds only the element's own nodes and delta_o = xi_1 + 1 reaches exactly
+    the first interior node, so every weight function of Table 1 gives 1/2 at
+    the two interface nodes and 1 elsewhere: all weightings are one smoother
+    on such levels."""
+    xb = W.uniform_breaks(4, 1.0)
+    sp = Space(xb, xb, p, PERIODIC)
+    ref = None
+    for wf in (1, 3, 5, 7, WF_TOPHAT, WF_ARITH):
+        w = SchwarzLevel(sp, 0, wf).subdomain_weights(1, 2)
+        if ref is None:
+            ref = w
+            w1 = np.ones(p + 1)
+            w1[0] = w1[-1] = 0.5
+            assert np.allclose(w, np.outer(w1, w1), atol=1e-15)
+        assert np.allclose(w, ref, atol=1e-15), wf
