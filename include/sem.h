@@ -95,6 +95,21 @@ typedef struct {
    * line (interface); the transition width at that interface is
    * alpha * delta_o.  NULL means 1 everywhere (the paper's weights). */
   const double *alpha_x, *alpha_y;
+  /* Optional per-element parameters (a project extension; the paper fixes
+   * one overlap per level and one transition width): host array
+   * elem_params[e][2] = (alpha_e, rho_e), e = ey * nx + ex, alpha_e in
+   * (0, 1], rho_e >= 0.  On level l > 0 element e's subdomain has
+   * n_o,e = ceil(rho_e p_l) layers, clamped to [1, p_l - 1] and to a width
+   * p_l + 1 + 2 n_o,e <= 48, and its weights are the weight function of
+   * Section 3.1 with delta = alpha_e delta_o(n_o,e) on both sides (unit
+   * weights for SEM_W_ARITH).  Neighbouring subdomains then need not share
+   * their transition zones, so the update is normalised node by node:
+   *   u += D^{-1} sum_s R_s^T W_s A_ss^{-1} R_s r,  D = sum_s R_s^T W_s R_s,
+   * which equals the paper's update when all elements carry equal
+   * parameters (D = 1) and the arithmetic mean for unit weights (D = C).
+   * When non-NULL, alpha_x / alpha_y must be NULL and the overlap rule is
+   * not used on levels l > 0 (sem_level_info reports the largest n_o,e). */
+  const float *elem_params;
 } sem_weights;
 
 /* Build all levels, operators, fast-diagonalisation factors, weights,
@@ -166,15 +181,29 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
                          const int32_t *ns1, const int32_t *ns2, int32_t *iters,
                          double *res_hist);
 
-/* Kernel timing for measurement: when enabled for `level`, every launch of
- * the fast-diagonalisation Schwarz kernel on that level (the dominant kernel
- * of the cycle) is bracketed by a pair of HIP events on the handle's stream.
- * sem_timing_read synchronises the stream and returns the number of timed
- * launches and their summed duration in milliseconds, then clears the
- * record.  At most 65536 launches are recorded between reads; later launches
- * are not timed.  on = 0 disables recording. */
+/* Kernel timing for measurement.  When enabled for `level`, the kernels of
+ * every Schwarz smoothing step (Algorithm 2's subdomain solves and weighted
+ * scatter), residual, restriction and prolongation on that level are timed
+ * with a pair of HIP events that the kernel dispatch itself records at the
+ * kernels' start and end (hipExtLaunchKernel), on the handle's stream: the
+ * time is the kernels' own, without dispatch gaps.  sem_timing_read_all
+ * synchronises the stream and writes, per kind (sem_timing_kind), the number
+ * of timed launches count[SEM_TIME_KINDS] and their summed duration in
+ * milliseconds total_ms[SEM_TIME_KINDS] (host arrays), then clears the
+ * record; sem_timing_read returns the Schwarz kind only.  At most 65536
+ * launches are recorded between reads; later launches are not timed.
+ * on = 0 disables recording.  SEM_EINVAL for level < 1 or null pointers. */
+typedef enum {
+  SEM_TIME_SCHWARZ = 0,   /* subdomain solves and weighted scatter      */
+  SEM_TIME_RESIDUAL = 1,  /* r = f - A u                                */
+  SEM_TIME_RESTRICT = 2,
+  SEM_TIME_PROLONG = 3,
+  SEM_TIME_APPLY = 4,     /* q = A p (no right-hand side), MGCG's product */
+  SEM_TIME_KINDS = 5
+} sem_timing_kind;
 sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on);
 sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms);
+sem_status sem_timing_read_all(sem_handle h, int64_t *count, double *total_ms);
 
 /* ------------------------------------------------------------------------
  * Learned Schwarz parameters (a project extension; the paper fixes the
@@ -239,6 +268,7 @@ sem_status sem_learned_params(const float *pred, int32_t nx, int32_t ny, int32_t
 
 /* Euclidean norm of the unknowns of a level-L array (synchronises). */
 sem_status sem_norm(sem_handle h, const double *x, double *out);
+
 
 const char *sem_strerror(sem_status s);
 const char *sem_last_error(sem_handle h);

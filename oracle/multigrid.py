@@ -28,7 +28,8 @@ import scipy.sparse.linalg as spla
 
 from .discretization import PERIODIC, Space, element_mean
 from .gll import gll, lagrange_matrix
-from .schwarz import ElementwiseSchwarzLevel, SchwarzLevel
+from .schwarz import ElementwiseSchwarzLevel, MultiplicativeSchwarzLevel, SchwarzLevel
+from .weights import WF_MULT
 
 OVERLAP_FIXED, OVERLAP_CEIL8, OVERLAP_FLOOR8, OVERLAP_CEIL2 = 0, 1, 2, 3
 
@@ -127,6 +128,9 @@ class Multigrid:
                 self.elem_no.append(no)
                 self.overlaps[l] = int(no.max())
                 self.schwarz.append(ElementwiseSchwarzLevel(self.spaces[l], no, alpha_e, wf))
+        elif wf == WF_MULT:
+            self.schwarz = [None] + [MultiplicativeSchwarzLevel(self.spaces[l], self.overlaps[l])
+                                     for l in range(1, self.L + 1)]
         else:
             self.schwarz = [None] + [
                 SchwarzLevel(self.spaces[l], self.overlaps[l], wf, alpha_x, alpha_y)

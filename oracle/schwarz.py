@@ -245,3 +245,44 @@ class ElementwiseSchwarzLevel:
             R = sp.zero_boundary(R)
             U = U + self.corrections(R, nubar)
         return U
+
+
+class MultiplicativeSchwarzLevel:
+    """Multiplicative Schwarz method (Section 3.1, Algorithm 1): the subdomain
+    problems are solved one after the other, each on the residual left by all
+    the corrections before it, without weights.  Sweep i visits the elements
+    in order e = 1 .. n_el when i is odd and in reverse when i is even, so an
+    even number of sweeps is a symmetric smoother.  Reading: the elements are
+    numbered row by row, e = ey nx + ex (x fastest).  Variable diffusion uses
+    B(nu) in the residual and nu_bar_s in the local solve, as the additive
+    method does."""
+
+    def __init__(self, space: Space, n_o: int):
+        self.space = space
+        self.n_o = n_o
+        ax, ay = space.ax, space.ay
+        self.sx = [Subdomain1D(ax, space.Lx, space.Mx, e, n_o) for e in range(ax.n)]
+        self.sy = [Subdomain1D(ay, space.Ly, space.My, e, n_o) for e in range(ay.n)]
+        self.inv = {}
+        for ey in range(ay.n):
+            for ex in range(ax.n):
+                k = (self.sy[ey].key(), self.sx[ex].key())
+                if k not in self.inv:
+                    self.inv[k] = np.linalg.inv(local_matrix(self.sy[ey], self.sx[ex]))
+        self.order = [(ey, ex) for ey in range(ay.n) for ex in range(ax.n)]
+
+    def smooth(self, U, F, n_it: int, NU=None, nubar=None):
+        sp = self.space
+        U = np.array(U, dtype=np.float64)
+        for i in range(1, n_it + 1):
+            seq = self.order if i % 2 == 1 else self.order[::-1]
+            for ey, ex in seq:
+                R = F - (sp.apply_A(U) if NU is None else sp.apply_B(U, NU))
+                sy, sx = self.sy[ey], self.sx[ex]
+                Rs = R[np.ix_(sy.glob, sx.glob)]
+                d = (self.inv[(sy.key(), sx.key())] @ Rs.ravel()).reshape(Rs.shape)
+                if nubar is not None:
+                    d = d / nubar[ey, ex]
+                U[np.ix_(sy.glob, sx.glob)] += d
+            U = sp.zero_boundary(U)
+        return U

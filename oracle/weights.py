@@ -20,9 +20,11 @@ import math
 
 import numpy as np
 
-# wf identifiers (negative values are the two non-polynomial cases of Table 1)
+# wf identifiers (negative values are the two non-polynomial cases of Table 1,
+# and the multiplicative method of Algorithm 1, which uses no weights)
 WF_TOPHAT = -1
 WF_ARITH = -2
+WF_MULT = -3
 
 TABLE1 = {
     1: lambda x: x,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sem.h"
+#include "common.h"
 #include "host_math.h"
 #include "kernels.h"
 
@@ -92,8 +93,25 @@ struct DirFdm {
   std::vector<double> wts;        // per element m
 };
 
+// Schwarz tables of the subdomains of one overlap value when every element
+// carries its own parameters (sem_weights.elem_params).
+template <typename T>
+struct FdmTab {
+  T *Sx = nullptr, *SxT = nullptr, *SyW = nullptr, *SyT = nullptr, *dinv = nullptr;
+  T *wel = nullptr;   // per element: 1-D weights along y, then along x
+};
+struct Seg {
+  int n_o = 0, m = 0, ntasks = 0, ntx = 0;
+  FdmTask *tasks = nullptr;
+  FdmTab<double> d;
+  FdmTab<float> f;
+};
+
 struct Level {
   int p = 1, n_o = 0, m = 0;
+  std::vector<Seg> segs;                     // per-element parameters: one per overlap value
+  double *dnorm = nullptr;                   // 1 / (sum of subdomain weights) per node
+  float *dnormf = nullptr;
   Grid g{};
   std::vector<double> xc, yc;     // node coordinates
   std::vector<double> nu_host;    // nodal nu (variable coefficient)
@@ -128,9 +146,11 @@ struct sem_ctx {
   double *partial = nullptr, *scal = nullptr;  // scal: device scalars
   // element widths and 1/nu_bar per element (element features)
   double *hx = nullptr, *hy = nullptr, *enuinv = nullptr, *enu = nullptr;  // enu: finest nodal nu
-  // optional event timing of the Schwarz kernel on one level
+  // optional kernel timing on one level: event pairs of timed launches, with
+  // the kind of launch (sem_timing_kind) of each pair
   int time_level = -1;
   std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
   size_t ev_used = 0;
   std::string err;
   // pinned host slots and events for reading residual norms asynchronously
@@ -161,7 +181,7 @@ int level_overlap(int rule, int n_o, int pl) {
 
 // Subdomain types, factors and weights along one direction (Section 3.1).
 DirFdm build_direction(const std::vector<double> &br, int p, int n_o, int periodic, int wf,
-                       const double *alpha) {
+                       const double *alpha, bool unweighted = false) {
   const int n = (int)br.size() - 1;
   const int m = p + 1 + 2 * n_o;
   const int N = periodic ? n * p : n * p + 1;
@@ -228,7 +248,9 @@ DirFdm build_direction(const std::vector<double> &br, int p, int n_o, int period
         bool v;
         int g = glob(e, k, v);
         if (!v) continue;
-        if (wf == SEM_W_ARITH) {
+        if (unweighted) {
+          we[k] = 1.0;   // per-element weights are applied by the kernel
+        } else if (wf == SEM_W_ARITH) {
           we[k] = 1.0 / count[g];
         } else {
           const int t = k - n_o;
@@ -295,6 +317,35 @@ DirFdm build_direction(const std::vector<double> &br, int p, int n_o, int period
     std::copy(we.begin(), we.end(), out.wts.begin() + (size_t)e * m);
   }
   return out;
+}
+
+// Work items of a level's Schwarz kernel: EPW = 64/m elements of one
+// subdomain type pair per wavefront, grouped by type pair anywhere in the
+// mesh; `only` (optional) restricts the list to a subset of the elements.
+std::vector<FdmTask> build_tasks(const DirFdm &fx, const DirFdm &fy, int nx, int ny, int m,
+                                 const std::vector<char> *only = nullptr) {
+  const int epw = std::min(64 / m, kTaskSlots);
+  std::vector<FdmTask> tasks;
+  for (int ty = 0; ty < fy.ntypes; ++ty)
+    for (int tx = 0; tx < fx.ntypes; ++tx) {
+      FdmTask cur{};
+      cur.ty = ty;
+      cur.tx = tx;
+      for (int ey = 0; ey < ny; ++ey) {
+        if (fy.type_of[ey] != ty) continue;
+        for (int ex = 0; ex < nx; ++ex) {
+          if (fx.type_of[ex] != tx) continue;
+          if (only && !(*only)[(size_t)ey * nx + ex]) continue;
+          cur.elem[cur.count++] = (ey << 16) | ex;
+          if (cur.count == epw) {
+            tasks.push_back(cur);
+            cur.count = 0;
+          }
+        }
+      }
+      if (cur.count) tasks.push_back(cur);
+    }
+  return tasks;
 }
 
 template <typename T>
@@ -399,6 +450,118 @@ Mat coarse_dense(const Level &L, const std::vector<double> &xb, const std::vecto
   return B;
 }
 
+// Overlap of an element with overlap ratio rho on a level of order p_l:
+// ceil(rho p_l), clamped to [1, p_l - 1] and to a subdomain width of at most
+// kMaxTile nodes.
+int element_overlap(double rho, int pl) {
+  int v = (int)std::ceil(rho * pl - 1e-12);
+  v = std::min(std::max(v, 1), std::min(pl - 1, (kMaxTile - pl - 1) / 2));
+  return std::max(v, 0);
+}
+
+// Per-element Schwarz parameters on one level: one segment of tables and
+// work items per distinct overlap, per-element 1-D weights, and the node
+// array 1/D of the Shepard normalisation (D = sum of the subdomain weights).
+void build_segments(sem_ctx *h, Level &lv, const std::vector<double> &xb,
+                    const std::vector<double> &yb, int per, int wf, const float *ep, bool mixed) {
+  const int nx = lv.g.nx, ny = lv.g.ny, p = lv.p;
+  const long ne = (long)nx * ny;
+  std::vector<int> no(ne);
+  for (long e = 0; e < ne; ++e) no[e] = element_overlap(ep[2 * e + 1], p);
+  std::vector<int> vals(no.begin(), no.end());
+  std::sort(vals.begin(), vals.end());
+  vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+  Vec xi, wq;
+  gll_rule(p, xi, wq);
+  const int R = lv.g.rows, Cc = lv.g.cols;
+  std::vector<double> Dsum((size_t)R * Cc, 0.0);
+  // extended coordinate of window position k (Section 3.1) and whether the
+  // node there is an unknown
+  auto ext = [&](int k, int n_o) {
+    const int t = k - n_o;
+    return t < 0 ? xi[p + t] - 2.0 : (t > p ? xi[t - p] + 2.0 : xi[t]);
+  };
+  for (int v : vals) {
+    Seg sg;
+    sg.n_o = v;
+    sg.m = p + 1 + 2 * v;
+    const int m = sg.m;
+    DirFdm fx = build_direction(xb, p, v, per, wf, nullptr, true);
+    DirFdm fy = build_direction(yb, p, v, per, wf, nullptr, true);
+    sg.ntx = fx.ntypes;
+    std::vector<double> dinv((size_t)fy.ntypes * fx.ntypes * m * m);
+    for (int ty = 0; ty < fy.ntypes; ++ty)
+      for (int tx = 0; tx < fx.ntypes; ++tx)
+        for (int a = 0; a < m; ++a)
+          for (int c = 0; c < m; ++c)
+            dinv[(((size_t)ty * fx.ntypes + tx) * m + a) * m + c] =
+                1.0 / (fy.lam[(size_t)ty * m + a] + fx.lam[(size_t)tx * m + c]);
+    std::vector<char> mine(ne, 0);
+    std::vector<double> wel((size_t)ne * 2 * m, 0.0);
+    const double delta = xi[v + 1] + 1.0;
+    for (int ey = 0; ey < ny; ++ey)
+      for (int ex = 0; ex < nx; ++ex) {
+        const long e = (long)ey * nx + ex;
+        if (no[e] != v) continue;
+        mine[e] = 1;
+        const double a = ep[2 * e];
+        double *wy = &wel[(size_t)e * 2 * m], *wx = wy + m;
+        std::vector<int> rows(m), cols(m);
+        for (int k = 0; k < m; ++k) {
+          int gr = ey * p - v + k, gc = ex * p - v + k;
+          bool vr, vc;
+          if (per) {
+            gr = ((gr % R) + R) % R;
+            gc = ((gc % Cc) + Cc) % Cc;
+            vr = vc = true;
+          } else {
+            vr = gr >= 1 && gr <= R - 2;
+            vc = gc >= 1 && gc <= Cc - 2;
+          }
+          rows[k] = vr ? gr : -1;
+          cols[k] = vc ? gc : -1;
+          const double x = ext(k, v);
+          if (vr)
+            wy[k] = wf == SEM_W_ARITH ? 1.0
+                                      : weight_fn(wf, x, a * delta, a * delta, !per && ey == 0,
+                                                  !per && ey == ny - 1);
+          if (vc)
+            wx[k] = wf == SEM_W_ARITH ? 1.0
+                                      : weight_fn(wf, x, a * delta, a * delta, !per && ex == 0,
+                                                  !per && ex == nx - 1);
+        }
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j < m; ++j)
+            if (rows[i] >= 0 && cols[j] >= 0) Dsum[(size_t)rows[i] * Cc + cols[j]] += wy[i] * wx[j];
+      }
+    std::vector<FdmTask> tasks = build_tasks(fx, fy, nx, ny, m, &mine);
+    sg.ntasks = (int)tasks.size();
+    if (sg.ntasks) {
+      h->pool.emplace_back(new DBuf());
+      h->pool.back()->alloc(tasks.size() * sizeof(FdmTask));
+      sg.tasks = h->pool.back()->as<FdmTask>();
+      HIP_OK(hipMemcpy(sg.tasks, tasks.data(), tasks.size() * sizeof(FdmTask),
+                       hipMemcpyHostToDevice));
+    }
+    auto fill = [&](auto &t, auto tag) {
+      using T = decltype(tag);
+      t.Sx = upload<T>(h->pool, fx.S);
+      t.SxT = upload<T>(h->pool, fx.ST);
+      t.SyW = upload<T>(h->pool, fy.SW);   // unweighted: W = 1 in build_direction
+      t.SyT = upload<T>(h->pool, fy.ST);
+      t.dinv = upload<T>(h->pool, dinv);
+      t.wel = upload<T>(h->pool, wel);
+    };
+    fill(sg.d, double());
+    if (mixed) fill(sg.f, float());
+    lv.segs.push_back(sg);
+  }
+  std::vector<double> dn((size_t)R * Cc, 0.0);
+  for (size_t i = 0; i < dn.size(); ++i) dn[i] = Dsum[i] > 0.0 ? 1.0 / Dsum[i] : 0.0;
+  lv.dnorm = upload<double>(h->pool, dn);
+  if (mixed) lv.dnormf = upload<float>(h->pool, dn);
+}
+
 void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
                 const sem_weights *wts, const double *nu) {
   if (!mesh || !ov || !wts || !mesh->xb || !mesh->yb) throw Fail{SEM_EINVAL, "null argument"};
@@ -416,6 +579,15 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     if (!(xb[i + 1] > xb[i])) throw Fail{SEM_EDOM, "x breaks not increasing"};
   for (int i = 0; i < ny; ++i)
     if (!(yb[i + 1] > yb[i])) throw Fail{SEM_EDOM, "y breaks not increasing"};
+  if (wts->elem_params) {
+    if (wts->alpha_x || wts->alpha_y)
+      throw Fail{SEM_EINVAL, "per-element parameters exclude per-line width scales"};
+    for (long e = 0; e < (long)nx * ny; ++e) {
+      const double a = wts->elem_params[2 * e], r = wts->elem_params[2 * e + 1];
+      if (!(std::isfinite(a) && a > 0.0 && a <= 1.0) || !(std::isfinite(r) && r >= 0.0))
+        throw Fail{SEM_EINVAL, "per-element parameters: alpha in (0, 1], rho >= 0"};
+    }
+  }
   for (const double *a : {wts->alpha_x, wts->alpha_y}) {
     if (!a) continue;
     const int n = (a == wts->alpha_x ? nx : ny) + 1;
@@ -442,6 +614,10 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     lv.p = orders[l];
     if (l == 0) {
       lv.n_o = 0;
+    } else if (wts->elem_params) {
+      lv.n_o = 0;
+      for (long e = 0; e < (long)nx * ny; ++e)
+        lv.n_o = std::max(lv.n_o, element_overlap(wts->elem_params[2 * e + 1], lv.p));
     } else if (ov->per_level) {
       lv.n_o = ov->per_level[l];
       if (lv.n_o < 0 || lv.n_o > lv.p - 1) throw Fail{SEM_EINVAL, "per-level overlap outside [0, p_l - 1]"};
@@ -538,7 +714,10 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     }
     DirFdm fx, fy;
     std::vector<double> dinv;
-    if (l > 0) {
+    const bool single = l > 0 && !wts->elem_params;
+    if (l > 0 && wts->elem_params)
+      build_segments(h, lv, xb, yb, per, wts->wf, wts->elem_params, mixed);
+    if (single) {
       fx = build_direction(xb, lv.p, lv.n_o, per, wts->wf, wts->alpha_x);
       fy = build_direction(yb, lv.p, lv.n_o, per, wts->wf, wts->alpha_y);
       const int m = lv.m;
@@ -551,27 +730,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
             for (int c = 0; c < m; ++c)
               dinv[(((size_t)ty * fx.ntypes + tx) * m + a) * m + c] =
                   1.0 / (fy.lam[(size_t)ty * m + a] + fx.lam[(size_t)tx * m + c]);
-      // work items: elements grouped by (ty, tx), EPW = 64/m per wavefront
-      const int epw = std::min(64 / m, kTaskSlots);
-      std::vector<FdmTask> tasks;
-      for (int ty = 0; ty < fy.ntypes; ++ty)
-        for (int tx = 0; tx < fx.ntypes; ++tx) {
-          FdmTask cur{};
-          cur.ty = ty;
-          cur.tx = tx;
-          for (int ey = 0; ey < ny; ++ey) {
-            if (fy.type_of[ey] != ty) continue;
-            for (int ex = 0; ex < nx; ++ex) {
-              if (fx.type_of[ex] != tx) continue;
-              cur.elem[cur.count++] = (ey << 16) | ex;
-              if (cur.count == epw) {
-                tasks.push_back(cur);
-                cur.count = 0;
-              }
-            }
-          }
-          if (cur.count) tasks.push_back(cur);
-        }
+      std::vector<FdmTask> tasks = build_tasks(fx, fy, nx, ny, m);
       lv.ntasks = (int)tasks.size();
       h->pool.emplace_back(new DBuf());
       h->pool.back()->alloc(tasks.size() * sizeof(FdmTask));
@@ -582,11 +741,11 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     std::vector<double> DTv((size_t)(lv.p + 1) * (lv.p + 1));
     for (int a = 0; a <= lv.p; ++a)
       for (int b = 0; b <= lv.p; ++b) DTv[(size_t)a * (lv.p + 1) + b] = D(b, a);
-    upload_tables<double>(h, lv, lv.td, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, l > 0 ? &fx : nullptr,
-                          l > 0 ? &fy : nullptr, dinv, ninv, E);
+    upload_tables<double>(h, lv, lv.td, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, single ? &fx : nullptr,
+                          single ? &fy : nullptr, dinv, ninv, E);
     if (mixed)
-      upload_tables<float>(h, lv, lv.tf, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, l > 0 ? &fx : nullptr,
-                           l > 0 ? &fy : nullptr, dinv, ninv, E);
+      upload_tables<float>(h, lv, lv.tf, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, single ? &fx : nullptr,
+                           single ? &fy : nullptr, dinv, ninv, E);
     // vectors
     const long n = lv.n();
     if (l < L) {
@@ -701,6 +860,22 @@ Tables<double> &tabs<double>(Level &L) { return L.td; }
 template <>
 Tables<float> &tabs<float>(Level &L) { return L.tf; }
 
+// Arms the kernel-timing events for the launches made while it lives, when
+// timing is enabled for level l (see sem_timing_enable).
+struct TimedLaunch {
+  bool on = false;
+  TimedLaunch(sem_ctx *h, int l, int kind) {
+    if (l != h->time_level || h->ev_used + 2 > h->ev.size()) return;
+    launch_timing() = LaunchTiming{h->ev[h->ev_used], h->ev[h->ev_used + 1]};
+    h->ev_kind[h->ev_used / 2] = kind;
+    h->ev_used += 2;
+    on = true;
+  }
+  ~TimedLaunch() {
+    if (on) launch_timing() = LaunchTiming{};
+  }
+};
+
 template <typename T>
 void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x = nullptr,
               double *dot_res = nullptr) {
@@ -708,33 +883,61 @@ void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x 
   Tables<T> &t = tabs<T>(L);
   ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT,
                     t.gy, t.gx, dot_x, dot_x ? h->partial : nullptr};
-  launch_residual<T>(a, h->stream);
+  {
+    TimedLaunch tl(h, l, f ? SEM_TIME_RESIDUAL : SEM_TIME_APPLY);
+    launch_residual<T>(a, h->stream);
+  }
   // dot_res = sum of dot_x * out, from the kernel's per-block partial sums
   // (without dot_res they stay in h->partial for the consumer to add)
   if (dot_x && dot_res) launch_reduce(h->partial, (int)residual_waves(L.g), dot_res, h->stream);
 }
 
 template <typename T>
+FdmTab<T> &seg_tabs(Seg &s);
+template <>
+FdmTab<double> &seg_tabs<double>(Seg &s) { return s.d; }
+template <>
+FdmTab<float> &seg_tabs<float>(Seg &s) { return s.f; }
+template <typename T>
+T *level_dnorm(Level &L);
+template <>
+double *level_dnorm<double>(Level &L) { return L.dnorm; }
+template <>
+float *level_dnorm<float>(Level &L) { return L.dnormf; }
+
+template <typename T>
+void launch_fdm_prec(sem_ctx *h, const FdmArgs<T> &a) {
+  if constexpr (std::is_same<T, float>::value) {
+    const bool mfma = h->precision == SEM_MIXED_BF16 || h->precision == SEM_MIXED_FP16;
+    if (mfma && a.m >= kMfmaMinTile) {
+      launch_fdm_mfma(a, h->precision == SEM_MIXED_FP16, h->stream);
+      return;
+    }
+  }
+  launch_fdm<T>(a, h->stream);
+}
+
+template <typename T>
 void fdm(sem_ctx *h, int l, const T *r, T *u) {
   Level &L = h->lev[l];
   Tables<T> &t = tabs<T>(L);
+  if (!L.segs.empty()) {
+    // per-element parameters: one launch per overlap value, all adding into u
+    TimedLaunch tl(h, l, SEM_TIME_SCHWARZ);
+    for (Seg &sg : L.segs) {
+      FdmTab<T> &st = seg_tabs<T>(sg);
+      FdmArgs<T> a{L.g, sg.n_o, sg.m, sg.tasks, sg.ntasks, r, u, st.Sx, st.SxT, st.SyW, st.SyT,
+                   st.dinv, sg.ntx, nullptr, t.nuinv};
+      a.wel = st.wel;
+      a.dnorm = level_dnorm<T>(L);
+      launch_fdm_prec<T>(h, a);
+    }
+    return;
+  }
   FdmArgs<T> a{L.g, L.n_o, L.m, L.tasks, L.ntasks, r, u, t.Sx, t.SxT, t.SyW, t.SyT, t.dinv, L.ntx,
                t.wx, t.nuinv};
-  const bool timed = (l == h->time_level) && h->ev_used + 2 <= h->ev.size();
-  if (timed) HIP_OK(hipEventRecord(h->ev[h->ev_used], h->stream));
-  if constexpr (std::is_same<T, float>::value) {
-    const bool mfma = h->precision == SEM_MIXED_BF16 || h->precision == SEM_MIXED_FP16;
-    if (mfma && L.m >= kMfmaMinTile)
-      launch_fdm_mfma(a, h->precision == SEM_MIXED_FP16, h->stream);
-    else
-      launch_fdm<T>(a, h->stream);
-  } else {
-    launch_fdm<T>(a, h->stream);
-  }
-  if (timed) {
-    HIP_OK(hipEventRecord(h->ev[h->ev_used + 1], h->stream));
-    h->ev_used += 2;
-  }
+  TimedLaunch tl(h, l, SEM_TIME_SCHWARZ);
+  launch_fdm_prec<T>(h, a);
 }
 
 // n_it sweeps of Algorithm 2; if u_is_zero the first residual is f itself.
@@ -754,6 +957,7 @@ void smooth(sem_ctx *h, int l, T *u, const T *f, T *rbuf, int n_it, bool u_is_ze
 template <typename T>
 void restrict_(sem_ctx *h, int l, const T *rf, T *fc, T *uc_zero) {
   Level &F = h->lev[l], &C = h->lev[l - 1];
+  TimedLaunch tl(h, l, SEM_TIME_RESTRICT);
   launch_restrict<T>(F.g, C.g, rf, fc, uc_zero, tabs<T>(F).ET, h->stream);
 }
 
@@ -761,6 +965,7 @@ void restrict_(sem_ctx *h, int l, const T *rf, T *fc, T *uc_zero) {
 template <typename T>
 void prolong_add(sem_ctx *h, int l, const T *uc, T *uf) {
   Level &F = h->lev[l], &C = h->lev[l - 1];
+  TimedLaunch tl(h, l, SEM_TIME_PROLONG);
   launch_prolong<T>(F.g, C.g, uc, uf, tabs<T>(F).E, h->stream);
 }
 
@@ -1143,6 +1348,7 @@ sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on) {
     if (on) {
       if (h->ev.empty()) {
         h->ev.resize(2 * 65536);
+        h->ev_kind.assign(65536, 0);
         for (auto &e : h->ev) HIP_OK(hipEventCreate(&e));
       }
       h->time_level = level;
@@ -1153,20 +1359,34 @@ sem_status sem_timing_enable(sem_handle h, int32_t level, int32_t on) {
   });
 }
 
-sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms) {
+sem_status sem_timing_read_all(sem_handle h, int64_t *count, double *total_ms) {
   if (!h || !count || !total_ms) return SEM_EINVAL;
   return guard(h, [&] {
     HIP_OK(hipStreamSynchronize(h->stream));
-    double tot = 0.0;
+    for (int k = 0; k < SEM_TIME_KINDS; ++k) {
+      count[k] = 0;
+      total_ms[k] = 0.0;
+    }
     for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
       float ms = 0.0f;
       HIP_OK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
-      tot += ms;
+      const int k = h->ev_kind[i / 2];
+      count[k] += 1;
+      total_ms[k] += ms;
     }
-    *count = (int64_t)(h->ev_used / 2);
-    *total_ms = tot;
     h->ev_used = 0;
   });
+}
+
+sem_status sem_timing_read(sem_handle h, int64_t *count, double *total_ms) {
+  if (!h || !count || !total_ms) return SEM_EINVAL;
+  int64_t c[SEM_TIME_KINDS];
+  double t[SEM_TIME_KINDS];
+  const sem_status st = sem_timing_read_all(h, c, t);
+  if (st != SEM_OK) return st;
+  *count = c[SEM_TIME_SCHWARZ];
+  *total_ms = t[SEM_TIME_SCHWARZ];
+  return SEM_OK;
 }
 
 sem_status sem_elem_features(sem_handle h, float *feat) {

@@ -220,7 +220,8 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
   // ---- stage 4: du = diag(w_y) S_y T3, lane = column j; weighted scatter-add ------
 #pragma unroll
   for (int a = 0; a < M; ++a) X[a] = tile[a * LS + j];
-  const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
+  const T *__restrict__ we = A.wel ? A.wel + ((long)ey * g.nx + ex) * 2 * M : nullptr;
+  const T wxj = (act && vc) ? (we ? we[M + j] : A.wx[(long)ex * M + j]) : T(0);
 #pragma unroll RU
   for (int i = 0; i < M; ++i) {
     T v;
@@ -236,7 +237,12 @@ __global__ __launch_bounds__(64) void k_fdm(FdmArgs<T> A) {
     } else {
       vr = gr >= 1 && gr <= g.rows - 2;
     }
-    if (act && vc && vr) atomic_add(&A.u[(long)gr * g.cols + gc], v * wxj);
+    if (act && vc && vr) {
+      const long node = (long)gr * g.cols + gc;
+      T c = v * wxj;
+      if (we) c *= we[i] * A.dnorm[node];
+      atomic_add(&A.u[node], c);
+    }
   }
 }
 
@@ -350,17 +356,19 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
 #pragma unroll
   for (int b = 0; b < M; ++b) X[b] = tile[j * LS + b];   // row j of T1
   __syncthreads();
-  // ---- stage 2: columns c of T2 = T1 S_x / (nu_bar (lambda_y + lambda_x)) ----------
+  // ---- stage 2: columns c of T2 = T1 S_x, divided by nu_bar (lambda_y + lambda_x)
+  // as the row is read back for stage 3 (the eigenvalue row's loads are all
+  // in flight together there, instead of one round trip per output) ----------------
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int c = decltype(lo)::value; c < decltype(hi)::value; ++c) {
-      const T v = rdot(3, c) * (d[c] * s);
+      const T v = rdot(3, c);
       if (has_tile) tile[j * LS + c] = v;
     }
   });
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c];   // row j of T2
+  for (int c = 0; c < M; ++c) X[c] = tile[j * LS + c] * (d[c] * s);   // row j of T2
   __syncthreads();
   // ---- stage 3: columns b of T3 = T2 S_x^T ----------------------------------------
   half([&](auto lo, auto hi) {
@@ -374,7 +382,8 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
   // ---- stage 4: rows i of du = diag(w_y) S_y T3 (lane = column j); scatter-add ----
 #pragma unroll
   for (int a = 0; a < M; ++a) X[a] = tile[a * LS + j];
-  const T wxj = (act && vc) ? A.wx[(long)ex * M + j] : T(0);
+  const T *__restrict__ we = A.wel ? A.wel + ((long)ey * g.nx + ex) * 2 * M : nullptr;
+  const T wxj = (act && vc) ? (we ? we[M + j] : A.wx[(long)ex * M + j]) : T(0);
   half([&](auto lo, auto hi) {
 #pragma unroll kRowsPerIter<T, M>
     for (int i = decltype(lo)::value; i < decltype(hi)::value; ++i) {
@@ -387,7 +396,12 @@ __global__ __launch_bounds__(128) void k_fdm2(FdmArgs<T> A) {
       } else {
         vr = gr >= 1 && gr <= g.rows - 2;
       }
-      if (act && vc && vr) atomic_add(&A.u[(long)gr * g.cols + gc], v * wxj);
+      if (act && vc && vr) {
+        const long node = (long)gr * g.cols + gc;
+        T c = v * wxj;
+        if (we) c *= we[i] * A.dnorm[node];
+        atomic_add(&A.u[node], c);
+      }
     }
   });
 }
@@ -398,9 +412,9 @@ template <typename T, int M>
 void launch_fdm_m(const FdmArgs<T> &a, hipStream_t s) {
   if (a.ntasks <= 0) return;
   if constexpr (fdm_two_waves<T, M>())
-    hipLaunchKernelGGL((k_fdm2<T, M>), dim3(a.ntasks), dim3(128), 0, s, a);
+    klaunch((k_fdm2<T, M>), dim3(a.ntasks), dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL((k_fdm<T, M>), dim3(a.ntasks), dim3(64), 0, s, a);
+    klaunch((k_fdm<T, M>), dim3(a.ntasks), dim3(64), 0, s, a);
 }
 
 }  // namespace sem

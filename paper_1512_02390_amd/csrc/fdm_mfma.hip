@@ -234,6 +234,7 @@ __global__ __launch_bounds__(64) void k_fdm_mfma(FdmArgs<float> A) {
     to_operands<Op, NB>(Y, Xa, E);
     chain<Op, NB>(Xa, BSxT, Y);     // du = Q S_x^T
     const float back = Op::kScaled ? ldexpf(1.f, E) : 1.f;
+    const float *__restrict__ we = A.wel ? A.wel + ((long)ey * g.nx + ex) * 2 * m : nullptr;
     // weighted scatter-add: block (I, J) holds rows 16I + r4 + j, columns 16J + c16
 #pragma unroll
     for (int J = 0; J < NB; ++J) {
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(64) void k_fdm_mfma(FdmArgs<float> A) {
       } else {
         okc = n < m && gc >= 1 && gc <= g.cols - 2;
       }
-      const float wxn = okc ? A.wx[(long)ex * m + n] * back : 0.f;
+      const float wxn = okc ? (we ? we[m + n] : A.wx[(long)ex * m + n]) * back : 0.f;
 #pragma unroll
       for (int I = 0; I < NB; ++I)
 #pragma unroll
@@ -260,7 +261,12 @@ __global__ __launch_bounds__(64) void k_fdm_mfma(FdmArgs<float> A) {
           } else {
             ok = okc && a < m && gr >= 1 && gr <= g.rows - 2;
           }
-          if (ok) atomic_add(&A.u[(long)gr * g.cols + gc], Y[I][J][j] * wxn);
+          if (ok) {
+            const long node = (long)gr * g.cols + gc;
+            float c = Y[I][J][j] * wxn;
+            if (we) c *= we[a] * A.dnorm[node];
+            atomic_add(&A.u[node], c);
+          }
         }
     }
   }
@@ -271,11 +277,11 @@ __global__ __launch_bounds__(64) void k_fdm_mfma(FdmArgs<float> A) {
 template <class Op>
 static void launch_op(const FdmArgs<float> &a, hipStream_t s) {
   if (a.m <= 16)
-    hipLaunchKernelGGL((k_fdm_mfma<Op, 1>), dim3(a.ntasks), dim3(64), 0, s, a);
+    klaunch((k_fdm_mfma<Op, 1>), dim3(a.ntasks), dim3(64), 0, s, a);
   else if (a.m <= 32)
-    hipLaunchKernelGGL((k_fdm_mfma<Op, 2>), dim3(a.ntasks), dim3(64), 0, s, a);
+    klaunch((k_fdm_mfma<Op, 2>), dim3(a.ntasks), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL((k_fdm_mfma<Op, 3>), dim3(a.ntasks), dim3(64), 0, s, a);
+    klaunch((k_fdm_mfma<Op, 3>), dim3(a.ntasks), dim3(64), 0, s, a);
 }
 
 void launch_fdm_mfma(const FdmArgs<float> &a, bool fp16, hipStream_t s) {

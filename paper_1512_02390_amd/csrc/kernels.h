@@ -69,6 +69,13 @@ struct FdmArgs {
   int32_t ntx;
   const T *wx;                    // per x-element m weights
   const T *nuinv;                 // per element 1/nu_bar or null
+  // Per-element weights (learned parameters): when non-null, element
+  // e = ey nx + ex has its own 1-D weights wel[e][0, m) along y and
+  // wel[e][m, 2m) along x (SyW then holds the unweighted S_y, and wx is not
+  // used), and every contribution is multiplied by the node's dnorm = 1/D,
+  // D the sum of the subdomain weights at the node (Shepard normalisation).
+  const T *wel = nullptr;
+  const T *dnorm = nullptr;
 };
 
 template <typename T>

@@ -3,6 +3,12 @@
 #include "kernels.h"
 
 namespace sem {
+
+LaunchTiming &launch_timing() {
+  static thread_local LaunchTiming t;
+  return t;
+}
+
 namespace {
 
 // ---------------------------------------------------------------------------

@@ -72,7 +72,10 @@ template <typename T, int P>
 __device__ __forceinline__ void load_col(const T *__restrict__ u, int row0, int col, const Grid &g,
                                          bool on, T (&seg)[P + 1]) {
 #pragma unroll
-  for (int b = 0; b <= P; ++b) seg[b] = on ? node_value(u, row0 + b, col, g.rows, g.cols, g.periodic) : T(0);
+  for (int b = 0; b <= P; ++b) {
+    const T v = node_value(u, row0 + b, on ? col : 1, g.rows, g.cols, g.periodic);
+    seg[b] = on ? v : T(0);
+  }
 }
 
 // Nodal coefficient at (row, col): periodic indices wrap, Dirichlet indices
@@ -215,17 +218,34 @@ __global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
     const cptr<T> Op = as_const(A.Lhat);
     const T sy = A.sy[ey];
-#pragma unroll rows_per_iter<T, P>()
-    for (int a = lo; a < hi; ++a) {
-      T yp = sy * udot<T, P + 1>(Op + a * (P + 1), yv);
+    // the right-hand side and dot-product operand of this wave's rows, all
+    // loaded before the first store (out may alias neither, but the compiler
+    // cannot tell, and would otherwise wait one memory round trip per row)
+    constexpr int HR = (P + NW - 1) / NW;
+    T fv[HR], xv[HR];
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+      const long idx = (long)(r0 + lo + t) * g.cols + gc;
+      const bool on = lo + t < hi;
+      fv[t] = (on && A.f) ? A.f[idx] : T(0);
+      xv[t] = (on && A.dot_x) ? A.dot_x[idx] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+      const int a = lo + t;
+      if (a >= hi) break;
+      // the row address passes an optimisation barrier: the unrolled loop
+      // then fetches one operator row at a time instead of all of them
+      const cptr<T> orow = as_const(opaque(A.Lhat + a * (P + 1)));
+      T yp = sy * udot<T, P + 1>(orow, yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
       const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
       const T au = myr * sxp(a, c) + mxc * yp;
-      T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
+      T v = A.f ? fv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
-      if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
+      dsum += (double)v * (double)xv[t];
     }
     if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
@@ -287,10 +307,18 @@ __global__ __launch_bounds__(64 * NW) void k_flux(ResidualArgs<T> A) {
     }
     if (col_lane && gc < g.cols) {
       T *out = A.gy + (long)ey * (P + 1) * g.cols + gc;
-#pragma unroll rows_per_iter<T, P>()
-      for (int b = lo; b < hi; ++b)
-        out[(long)b * g.cols] = udot<T, P + 1>(as_const(A.D) + b * (P + 1), seg) *
-                                coef_value(A.nu, r0 + b, gc, g.rows, g.cols, per);
+      // the coefficients of this wave's rows, loaded before the first store
+      constexpr int HB = (P + 1 + NW - 1) / NW;
+      T nv[HB];
+#pragma unroll
+      for (int t = 0; t < HB; ++t)
+        nv[t] = lo + t < hi ? coef_value(A.nu, r0 + lo + t, gc, g.rows, g.cols, per) : T(0);
+#pragma unroll
+      for (int t = 0; t < HB; ++t) {
+        const int b = lo + t;
+        if (b >= hi) break;
+        out[(long)b * g.cols] = udot<T, P + 1>(as_const(opaque(A.D + b * (P + 1))), seg) * nv[t];
+      }
     }
     // right end of the strip (first column of the next strip)
     if (w == 0 && lane < P && c0 + W <= last_col)
@@ -307,10 +335,17 @@ __global__ __launch_bounds__(64 * NW) void k_flux(ResidualArgs<T> A) {
       for (int d = 0; d <= P; ++d) seg[d] = su[a][q * P + d];
       const int row = r0 + a;
       T *out = A.gx + (long)ex * (P + 1) * g.rows + row;
-#pragma unroll rows_per_iter<T, P>()
-      for (int c = lo; c < hi; ++c)
-        out[(long)c * g.rows] = udot<T, P + 1>(as_const(A.D) + c * (P + 1), seg) *
-                                coef_value(A.nuT, ex * P + c, row, g.cols, g.rows, per);
+      constexpr int HB = (P + 1 + NW - 1) / NW;
+      T nv[HB];
+#pragma unroll
+      for (int t = 0; t < HB; ++t)
+        nv[t] = lo + t < hi ? coef_value(A.nuT, ex * P + lo + t, row, g.cols, g.rows, per) : T(0);
+#pragma unroll
+      for (int t = 0; t < HB; ++t) {
+        const int c = lo + t;
+        if (c >= hi) break;
+        out[(long)c * g.rows] = udot<T, P + 1>(as_const(opaque(A.D + c * (P + 1))), seg) * nv[t];
+      }
     }
   }
 }
@@ -388,17 +423,30 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
     const T sy = A.sy[ey];
-#pragma unroll rows_per_iter<T, P>()
-    for (int a = lo; a < hi; ++a) {
-      T yp = sy * udot<T, P + 1>(as_const(A.DT) + a * (P + 1), yv);
+    // right-hand side and dot operand loaded before the first store (see k_residual)
+    constexpr int HR = (P + NW - 1) / NW;
+    T fv[HR], xv[HR];
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+      const long idx = (long)(r0 + lo + t) * g.cols + gc;
+      const bool on = lo + t < hi;
+      fv[t] = (on && A.f) ? A.f[idx] : T(0);
+      xv[t] = (on && A.dot_x) ? A.dot_x[idx] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+      const int a = lo + t;
+      if (a >= hi) break;
+      const cptr<T> orow = as_const(opaque(A.DT + a * (P + 1)));
+      T yp = sy * udot<T, P + 1>(orow, yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
       const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
       const T au = myr * sxp[a][c] + mxc * yp;
-      T v = A.f ? A.f[(long)row * g.cols + gc] - au : au;
+      T v = A.f ? fv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
-      if (A.dot_x) dsum += (double)v * (double)A.dot_x[(long)row * g.cols + gc];
+      dsum += (double)v * (double)xv[t];
     }
     if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
@@ -427,11 +475,11 @@ void launch_residual_p(const ResidualArgs<T> &a, hipStream_t s) {
   dim3 grid(ceil_div(a.g.nx, NE), a.g.ny);
   if (a.nu) {
     constexpr int NW = nu_waves<P>();
-    hipLaunchKernelGGL((k_flux<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
-    hipLaunchKernelGGL((k_residual_nu<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
+    klaunch((k_flux<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
+    klaunch((k_residual_nu<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   } else {
     constexpr int NW = poisson_waves<P>();
-    hipLaunchKernelGGL((k_residual<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
+    klaunch((k_residual<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   }
 }
 

@@ -72,11 +72,11 @@ __global__ __launch_bounds__(64 * NW) void k_restrict(Grid gf, Grid gc, const T 
     T seg[PF + 1];
 #pragma unroll
     for (int a = 0; a <= PF; ++a)
-      seg[a] = colok ? node_value(rf, r0 + a, col, gf.rows, gf.cols, per) : T(0);
+      seg[a] = colok ? node_value_guarded(rf, r0 + a, col, gf.rows, gf.cols, per) : T(0);
     T segb[PF + 1];
 #pragma unroll
     for (int a = 0; a <= PF; ++a)
-      segb[a] = (colok && has_below && a < PF) ? node_value(rf, r0 - PF + a, col, gf.rows, gf.cols, per)
+      segb[a] = (colok && has_below && a < PF) ? node_value_guarded(rf, r0 - PF + a, col, gf.rows, gf.cols, per)
                                                : T(0);
 #pragma unroll 1
     for (int b = 0; b < PC; ++b) st[b][k] = tdot<T, PF + 1>(as_const(ET) + b * (PF + 1), seg);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(64 * NW) void k_prolong(Grid gf, Grid gc, const T *
       T seg[PC + 1];
 #pragma unroll
       for (int c = 0; c <= PC; ++c)
-        seg[c] = node_value(uc, ey * PC + b, ex * PC + c, gc.rows, gc.cols, per);
+        seg[c] = node_value_guarded(uc, ey * PC + b, ex * PC + c, gc.rows, gc.cols, per);
 #pragma unroll 1
       for (int a = alo; a < ahi; ++a)
         st[b][q * PF + a] = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
@@ -169,10 +169,17 @@ __global__ __launch_bounds__(64 * NW) void k_prolong(Grid gf, Grid gc, const T *
 #pragma unroll
       for (int b = 0; b <= PC; ++b) seg[b] = st[b][c];
       T *out = uf + (long)r0 * gf.cols + col;
-#pragma unroll 1
-      for (int a = alo; a < ahi; ++a) {
+      // this wave's fine rows of u, loaded together before any store
+      constexpr int HA = (PF + NW - 1) / NW;
+      T ov[HA];
+#pragma unroll
+      for (int t = 0; t < HA; ++t) ov[t] = alo + t < ahi ? out[(long)(alo + t) * gf.cols] : T(0);
+#pragma unroll
+      for (int t = 0; t < HA; ++t) {
+        const int a = alo + t;
+        if (a >= ahi) break;
         const T v = tdot<T, PC + 1>(as_const(E) + a * (PC + 1), seg);
-        if (per || r0 + a > 0) out[(long)a * gf.cols] += v;
+        if (per || r0 + a > 0) out[(long)a * gf.cols] = ov[t] + v;
       }
     }
   }
@@ -186,7 +193,7 @@ void launch_restrict_p(const Grid &gf, const Grid &gc, const T *rf, T *fc, T *uc
   constexpr int NE = 64 / PF;
   constexpr int NW = transfer_waves<PF>();
   dim3 grid(ceil_div(gf.nx, NE), gf.ny);
-  hipLaunchKernelGGL((k_restrict<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, rf, fc, uc_zero,
+  klaunch((k_restrict<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, rf, fc, uc_zero,
                      ET);
 }
 
@@ -196,7 +203,7 @@ void launch_prolong_p(const Grid &gf, const Grid &gc, const T *uc, T *uf, const 
   constexpr int NE = 64 / PF;
   constexpr int NW = transfer_waves<PF>();
   dim3 grid(ceil_div(gf.nx, NE), gf.ny);
-  hipLaunchKernelGGL((k_prolong<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, uc, uf, E);
+  klaunch((k_prolong<T, PF, NW>), grid, dim3(64 * NW), 0, s, gf, gc, uc, uf, E);
 }
 
 }  // namespace sem

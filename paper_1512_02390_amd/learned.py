@@ -13,10 +13,13 @@ the library:
      iteration in finest-operator units, see ``cycle_cost``); every element
      of the patch becomes one sample (its features, that label);
   2. training: the library's MLP kernels (forward, backward, Adam) on the GPU;
-  3. inference: element features and the forward pass on the GPU, reduced to
-     per-level overlaps and per-grid-line width scales by sem_learned_params;
-     the paper's parameters are the fallback when the prediction is unusable
-     or the learned solve fails.
+  3. inference: element features and the forward pass on the GPU; each
+     element's prediction (alpha_e, rho_e) goes to the library either as its
+     own parameters (sem_weights.elem_params: per-element overlap and
+     transition width inside the Schwarz kernels, Shepard-normalised) or
+     reduced to one overlap per level and one width scale per grid line
+     (sem_learned_params); the paper's parameters are the fallback when the
+     prediction is unusable or the learned solve fails.
 """
 from __future__ import annotations
 
@@ -156,27 +159,47 @@ def train(X, T, steps: int = 1500, lr: float = 3e-3, seed: int = W.SEED_MLP):
     return net, hist
 
 
-def predict(solver: Solver, net: MLP, nx: int, ny: int, p: int, bc: int):
-    """(overlaps, alpha_x, alpha_y, per-element predictions) for a problem,
-    or None when the prediction is unusable (the caller then keeps the
-    paper's parameters)."""
-    pred = net.forward(solver.elem_features()).cpu().numpy()
-    try:
-        ov, ax, ay = learned_params(pred, nx, ny, p, bc)
-    except SemError:
+def elem_params_of(pred) -> np.ndarray | None:
+    """Per-element (alpha_e, rho_e) from network outputs (alpha, q = 2 rho):
+    alpha clipped to [0.1, 1]; None when a prediction is not finite."""
+    pred = np.asarray(pred, dtype=np.float64)
+    if not np.all(np.isfinite(pred)):
         return None
-    return ov, ax, ay, pred
+    return np.stack([np.clip(pred[:, 0], 0.1, 1.0), np.maximum(0.5 * pred[:, 1], 0.0)], axis=1)
 
 
-def solver_with_learned(xb, yb, p: int, bc: int, NU, net: MLP, precision: int = 0):
+def predict(solver: Solver, net: MLP):
+    """Per-element parameters (n_e, 2) for a problem, or None when the
+    prediction is unusable (the caller then keeps the paper's parameters)."""
+    pred = net.forward(solver.elem_features()).cpu().numpy()
+    return elem_params_of(pred)
+
+
+def solver_with_learned(xb, yb, p: int, bc: int, NU, net: MLP, precision: int = 0,
+                        mode: str = "level"):
     """Solver with learned parameters, or the paper's (ceil(p_l/8), alpha = 1)
-    when the prediction is unusable.  Returns (solver, params or None)."""
+    when the prediction is unusable.  Returns (solver, per-element parameters
+    (n_e, 2) or None).
+
+    mode "element": every element keeps its own prediction (overlap and width
+    per subdomain inside the Schwarz kernels, Shepard-normalised).
+    mode "level": the predictions are reduced by the library
+    (sem_learned_params) to one overlap per level (from the mean ratio) and
+    one width scale per grid line -- on the variable-diffusion workloads this
+    is the mode that lowers the iteration count (the network's smaller
+    overlaps on the square elements cost iterations when kept per element)."""
     base = Solver(xb, yb, p, bc, 1, 1, 5, nu=NU)
-    got = predict(base, net, len(xb) - 1, len(yb) - 1, p, bc)
+    ep = predict(base, net)
     base.close()
-    if got is None:
+    if ep is None:
         return Solver(xb, yb, p, bc, 1, 1, 5, nu=NU, precision=precision), None
-    ov, ax, ay, _ = got
+    if mode == "element":
+        return Solver(xb, yb, p, bc, 1, 1, 5, nu=NU, precision=precision, elem_params=ep), ep
+    pred = np.stack([ep[:, 0], 2.0 * ep[:, 1]], axis=1)
+    try:
+        ov, ax, ay = learned_params(pred, len(xb) - 1, len(yb) - 1, p, bc)
+    except SemError:
+        return Solver(xb, yb, p, bc, 1, 1, 5, nu=NU, precision=precision), None
     s = Solver(xb, yb, p, bc, 0, 1, 5, nu=NU, precision=precision, overlaps=ov,
                alpha_x=ax, alpha_y=ay)
-    return s, (ov, ax, ay)
+    return s, ep

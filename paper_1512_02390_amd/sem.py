@@ -26,7 +26,8 @@ STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_EDOM", -3: "SEM_ENOMEM", -4: "
 EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_node_coords",
            "sem_mass", "sem_residual", "sem_schwarz_smooth", "sem_restrict", "sem_prolong_add",
            "sem_coarse_solve", "sem_vcycle", "sem_pcg_solve", "sem_norm", "sem_strerror",
-           "sem_last_error", "sem_timing_enable", "sem_timing_read", "sem_elem_features",
+           "sem_last_error", "sem_timing_enable", "sem_timing_read", "sem_timing_read_all",
+           "sem_elem_features",
            "sem_mlp_num_params", "sem_mlp_create", "sem_mlp_destroy", "sem_mlp_forward",
            "sem_mlp_gradient", "sem_mlp_train_step", "sem_mlp_get_params",
            "sem_learned_params"]
@@ -49,7 +50,7 @@ class _Overlap(C.Structure):
 
 class _Weights(C.Structure):
     _fields_ = [("wf", C.c_int32), ("alpha_x", C.POINTER(C.c_double)),
-                ("alpha_y", C.POINTER(C.c_double))]
+                ("alpha_y", C.POINTER(C.c_double)), ("elem_params", C.POINTER(C.c_float))]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
     lib.sem_timing_enable.argtypes = [P, I32, I32]
     lib.sem_timing_read.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
+    lib.sem_timing_read_all.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
     F = C.POINTER(C.c_float)
     lib.sem_elem_features.argtypes = [P, P]
     lib.sem_mlp_num_params.argtypes = [I32, I32, I32, C.POINTER(I64)]
@@ -125,7 +127,9 @@ class Solver:
 
     def __init__(self, xb, yb, p: int, bc: int = BC_DIRICHLET, overlap_rule: int = NO_FIXED,
                  n_o: int = 1, wf: int = 5, nu=None, precision: int = FP64, alpha_x=None,
-                 alpha_y=None, stream=None, overlaps=None):
+                 alpha_y=None, stream=None, overlaps=None, elem_params=None):
+        """elem_params: optional (n_e, 2) array of per-element (alpha_e, rho_e),
+        e = ey * nx + ex (see sem_weights in include/sem.h)."""
         import torch
         self.lib = load_library()
         self.torch = torch
@@ -138,8 +142,11 @@ class Solver:
         ov = _Overlap(overlap_rule, n_o, self._ovl)
         self._ax = None if alpha_x is None else np.ascontiguousarray(alpha_x, dtype=np.float64)
         self._ay = None if alpha_y is None else np.ascontiguousarray(alpha_y, dtype=np.float64)
+        self._ep = None if elem_params is None else np.ascontiguousarray(
+            elem_params, dtype=np.float32).reshape(-1)
         wts = _Weights(wf, None if self._ax is None else self._ax.ctypes.data_as(dp),
-                       None if self._ay is None else self._ay.ctypes.data_as(dp))
+                       None if self._ay is None else self._ay.ctypes.data_as(dp),
+                       None if self._ep is None else self._ep.ctypes.data_as(C.POINTER(C.c_float)))
         nu_host = None
         if nu is not None:
             nu_host = np.ascontiguousarray(nu, dtype=np.float64)
@@ -243,6 +250,17 @@ class Solver:
         n, ms = C.c_int64(), C.c_double()
         self._check(self.lib.sem_timing_read(self.h, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+    TIME_KINDS = ("schwarz", "residual", "restrict", "prolong", "apply")
+
+    def timing_read_all(self):
+        """{kind: (number of timed launches, summed milliseconds)} for the
+        Schwarz, residual, restriction, prolongation and operator-product
+        kernels of the timed level (the record is cleared)."""
+        n = (C.c_int64 * len(self.TIME_KINDS))()
+        ms = (C.c_double * len(self.TIME_KINDS))()
+        self._check(self.lib.sem_timing_read_all(self.h, n, ms))
+        return {k: (n[i], ms[i]) for i, k in enumerate(self.TIME_KINDS)}
 
     def norm(self, x) -> float:
         out = C.c_double()

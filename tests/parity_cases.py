@@ -27,6 +27,7 @@ class Case:
     varnu: bool = False
     overlaps: tuple | None = None   # explicit n_o per level (entry 0 unused)
     alpha_seed: int | None = None   # random width scales per grid line in [0.2, 1]
+    elem_seed: int | None = None    # random per-element (alpha_e, rho_e)
 
     def breaks(self):
         if self.stretched:
@@ -47,6 +48,16 @@ class Case:
         if self.bc == W.BC_PERIODIC:
             ax[-1], ay[-1] = ax[0], ay[0]
         return ax, ay
+
+    def elem_params(self):
+        """(n_e, 2) per-element (alpha_e, rho_e), e = ey * nx + ex, rounded to
+        FP32 as the library receives them; or None."""
+        if self.elem_seed is None:
+            return None
+        g = W.rng(self.elem_seed)
+        a = g.uniform(0.2, 1.0, self.nx * self.ny)
+        r = g.uniform(0.0, 0.5, self.nx * self.ny)
+        return np.stack([a, r], axis=1).astype(np.float32).astype(np.float64)
 
 
 CASES = [
@@ -74,6 +85,12 @@ CASES = [
     # the seventh-order weight function of Table 1
     Case("per_p4_no1_septic", 4, 3, 4, P, wf=7),
     Case("dir_p16_ceil8_septic", 3, 2, 16, D, rule=CEIL8, wf=7),
+    # per-element overlaps and widths with Shepard normalisation
+    Case("dir_p8_elem_stretch", 5, 4, 8, D, stretched=True, elem_seed=21),
+    Case("per_p6_elem_cubic", 4, 5, 6, P, wf=3, elem_seed=22),
+    Case("dir_p12_elem_varnu_stretch", 3, 4, 12, D, stretched=True, varnu=True, elem_seed=23),
+    Case("dir_p16_elem_arith", 3, 3, 16, D, wf=ARITH, elem_seed=24),
+    Case("dir_p32_elem", 2, 2, 32, D, elem_seed=25),
 ]
 
 
@@ -91,8 +108,11 @@ def build_oracle(case: Case):
         top = Space(xb, yb, case.p, case.bc)
         NU = W.nodal(nu.nu, top.x(), top.y())
     ax, ay = case.alphas()
+    ep = case.elem_params()
+    if ep is not None:
+        ep = (ep[:, 0].reshape(case.ny, case.nx), ep[:, 1].reshape(case.ny, case.nx))
     return Multigrid(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, NU=NU,
-                     alpha_x=ax, alpha_y=ay, overlaps=case.overlaps), NU
+                     alpha_x=ax, alpha_y=ay, overlaps=case.overlaps, elem_params=ep), NU
 
 
 def build_gpu(case: Case, NU=None, precision=0):
@@ -100,7 +120,8 @@ def build_gpu(case: Case, NU=None, precision=0):
     xb, yb = case.breaks()
     ax, ay = case.alphas()
     return Solver(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, nu=NU,
-                  precision=precision, overlaps=case.overlaps, alpha_x=ax, alpha_y=ay)
+                  precision=precision, overlaps=case.overlaps, alpha_x=ax, alpha_y=ay,
+                  elem_params=case.elem_params())
 
 
 def rel_err(a, b) -> float:

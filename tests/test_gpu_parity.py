@@ -1,7 +1,10 @@
 """GPU parity: every entry point of the C-ABI against the oracle on the same
 seeded inputs, element by element, FP64 tolerance 1e-12 relative to the
 largest entry (operators with atomic accumulation differ from the oracle
-only by rounding order)."""
+only by rounding order).  The same bound holds for the coarse solve, three
+V-cycles and the whole MGCG solve (residual history relative to ||r_0||, final
+iterate relative to its largest entry): measured differences are at most
+1e-13 on every case."""
 import sys
 
 import numpy as np
@@ -102,7 +105,7 @@ def test_coarse_solve(pair):
     F = W.random_nodal(s0.shape, case.bc, 80)
     u0 = gpu.zeros(0)
     gpu.coarse_solve(_dev(F), u0)
-    assert rel_err(_host(u0), mg.coarse_solve(F)) < 1e-11
+    assert rel_err(_host(u0), mg.coarse_solve(F)) < TOL
 
 
 def test_vcycle(pair):
@@ -120,7 +123,7 @@ def test_vcycle(pair):
         U = mg.vcycle(U, F, ns1, ns2)
         gpu.vcycle(u, f, ns1, ns2)
         err = rel_err(_host(u), U)
-        assert err < 1e-11, (k, err)
+        assert err < TOL, (k, err)
 
 
 def test_pcg(pair):
@@ -133,12 +136,12 @@ def test_pcg(pair):
     u = _dev(U0)
     it, hist, ok = gpu.pcg_solve(u, _dev(F), 60, 1e-10)
     assert ok and it == it_ref
-    assert np.allclose(hist, hist_ref, rtol=1e-7, atol=1e-12 * hist_ref[0])
+    assert np.abs(hist - hist_ref).max() <= TOL * hist_ref[0]
     Ug = _host(u)
     if case.bc == P:
         Ug = Ug - Ug.mean()
         Uref = Uref - Uref.mean()
-    assert rel_err(Ug, Uref) < 1e-9
+    assert rel_err(Ug, Uref) < TOL
 
 
 def test_pcg_degenerate_cases():

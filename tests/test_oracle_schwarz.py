@@ -339,3 +339,47 @@ def test_zero_overlap_weight_functions_coincide(p):
             w1[0] = w1[-1] = 0.5
             assert np.allclose(w, np.outer(w1, w1), atol=1e-15)
         assert np.allclose(w, ref, atol=1e-15), wf
+
+
+# ---------------------------------------------------------------------------
+# Multiplicative Schwarz (Algorithm 1)
+# ---------------------------------------------------------------------------
+from oracle.schwarz import MultiplicativeSchwarzLevel  # noqa: E402
+
+
+def test_multiplicative_single_element_is_exact_solve():
+    sp = Space([0.0, 1.0], [0.0, 2.0], 7, DIRICHLET)
+    lev = MultiplicativeSchwarzLevel(sp, 3)
+    F = W.random_nodal(sp.shape, DIRICHLET, 3)
+    U = lev.smooth(np.zeros(sp.shape), F, 1)
+    assert np.abs(F - sp.apply_A(U))[sp.mask].max() < 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("bc,n_o", [(DIRICHLET, 1), (PERIODIC, 2)])
+def test_multiplicative_even_sweeps_are_symmetric(bc, n_o):
+    """Section 3.1: one multiplicative sweep is a non-symmetric operator, but
+    two sweeps, the second in reverse order, are symmetric: the error
+    propagation E (u -> u after the sweeps with f = 0) is self-adjoint in the
+    energy inner product, A E = E^T A, while one sweep is not."""
+    xb = W.geometric_breaks(3, 0.3, 2.0)
+    yb = W.uniform_breaks(3, 1.0)
+    sp = Space(xb, yb, 4, bc)
+    lev = MultiplicativeSchwarzLevel(sp, n_o)
+    A = sp.dense_B(np.ones(sp.shape))
+    n = int(sp.mask.sum())
+
+    def E_of(n_it):
+        E = np.zeros((n, n))
+        for k in range(n):
+            U = np.zeros(sp.shape)
+            U[sp.mask] = np.eye(n)[k]
+            E[:, k] = lev.smooth(U, np.zeros(sp.shape), n_it)[sp.mask]
+        return E
+
+    E2, E1 = E_of(2), E_of(1)
+    AE2, AE1 = A @ E2, A @ E1
+    assert np.abs(AE2 - AE2.T).max() < 1e-11 * np.abs(AE2).max()
+    assert np.abs(AE1 - AE1.T).max() > 1e-3 * np.abs(AE1).max()
+    # and the smoother contracts in the energy norm
+    lam = np.linalg.eigvals(E2)
+    assert np.max(np.abs(lam)) < 1.0 + 1e-12

@@ -64,12 +64,12 @@ def test_kernel_stats_summary(tmp_path):
 
 def test_kernel_hash_ignores_comments_and_layout():
     import bench
-    files = ("fdm_impl.h", "fdm_mfma.hip", "kernels.h", "common.h")
+    files = bench.KERNEL_SOURCES
     base = {f: "int a = 1;\nint b = 2;\n" for f in files}
     commented = dict(base)
     commented["fdm_impl.h"] = "// header\nint a = 1;   /* one */\n\n  int b = 2; // two\n"
     changed = dict(base)
-    changed["kernels.h"] = "int a = 1;\nint b = 3;\n"
+    changed["residual_impl.h"] = "int a = 1;\nint b = 3;\n"
     h = bench.kernel_source_hash(base)
     assert bench.kernel_source_hash(commented) == h
     assert bench.kernel_source_hash(changed) != h
