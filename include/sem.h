@@ -269,6 +269,16 @@ sem_status sem_learned_params(const float *pred, int32_t nx, int32_t ny, int32_t
 /* Euclidean norm of the unknowns of a level-L array (synchronises). */
 sem_status sem_norm(sem_handle h, const double *x, double *out);
 
+/* sem_norm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result from the same kernels, but the reduction's partial sums live
+ * in a fixed device array of the library (520 doubles, about 4 KB, one copy
+ * per GPU, resolved by sem_setup and held until the process ends) instead of
+ * the handle's buffer.  The call allocates nothing.  Any array size is
+ * accepted: the reduction never uses more than 512 partial sums.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (several streams or threads) race.
+ * SEM_EINVAL for null arguments, SEM_EHIP when a runtime call fails. */
+sem_status sem_norm_noalloc(sem_handle h, const double *x, double *out);
 
 const char *sem_strerror(sem_status s);
 const char *sem_last_error(sem_handle h);

@@ -17,6 +17,7 @@
 #include "../../include/sem.h"
 #include "common.h"
 #include "host_math.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace sem;
@@ -847,6 +848,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
                          hipHostMallocDefault));
     for (hipEvent_t &e : h->nev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  if (!noalloc_prepare()) throw Fail{SEM_EHIP, "device symbol lookup failed"};
   HIP_OK(hipDeviceSynchronize());
 }
 
@@ -1397,6 +1399,22 @@ sem_status sem_elem_features(sem_handle h, float *feat) {
                     h->stream);
   });
 }
+
+}  // extern "C"
+
+namespace sem {
+bool handle_top(sem_handle h, hipStream_t *stream, long *nodes) {
+  if (!h || h->lev.empty()) return false;
+  *stream = h->stream;
+  *nodes = h->lev.back().n();
+  return true;
+}
+void handle_error(sem_handle h, const char *msg) {
+  if (h) h->err = msg;
+}
+}  // namespace sem
+
+extern "C" {
 
 sem_status sem_norm(sem_handle h, const double *x, double *out) {
   if (!h || !x || !out) return SEM_EINVAL;

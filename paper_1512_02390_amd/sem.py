@@ -30,7 +30,7 @@ EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_
            "sem_elem_features",
            "sem_mlp_num_params", "sem_mlp_create", "sem_mlp_destroy", "sem_mlp_forward",
            "sem_mlp_gradient", "sem_mlp_train_step", "sem_mlp_get_params",
-           "sem_learned_params"]
+           "sem_learned_params", "sem_norm_noalloc"]
 
 
 class SemError(RuntimeError):
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     lib.sem_pcg_solve.argtypes = [P, P, P, I32, D, C.POINTER(I32), C.POINTER(I32),
                                   C.POINTER(I32), C.POINTER(D)]
     lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
+    lib.sem_norm_noalloc.argtypes = [P, P, C.POINTER(D)]
     lib.sem_timing_enable.argtypes = [P, I32, I32]
     lib.sem_timing_read.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
     lib.sem_timing_read_all.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
@@ -265,6 +266,12 @@ class Solver:
     def norm(self, x) -> float:
         out = C.c_double()
         self._check(self.lib.sem_norm(self.h, _ptr(x), C.byref(out)))
+        return out.value
+
+    def norm_noalloc(self, x) -> float:
+        """norm() through the allocation-free entry point."""
+        out = C.c_double()
+        self._check(self.lib.sem_norm_noalloc(self.h, _ptr(x), C.byref(out)))
         return out.value
 
     def elem_features(self):
