@@ -28,7 +28,8 @@ import scipy.sparse.linalg as spla
 
 from .discretization import PERIODIC, Space, element_mean
 from .gll import gll, lagrange_matrix
-from .schwarz import ElementwiseSchwarzLevel, MultiplicativeSchwarzLevel, SchwarzLevel
+from .schwarz import (ElementwiseSchwarzLevel, MultiplicativeSchwarzLevel, SchwarzLevel,
+                      SeparableSchwarzLevel)
 from .weights import WF_MULT
 
 OVERLAP_FIXED, OVERLAP_CEIL8, OVERLAP_FLOOR8, OVERLAP_CEIL2 = 0, 1, 2, 3
@@ -93,11 +94,14 @@ def interpolate_nodal(space_from: Space, space_to: Space, V) -> np.ndarray:
 class Multigrid:
     def __init__(self, xb, yb, p: int, bc: int, overlap_rule: int = OVERLAP_FIXED,
                  n_o: int = 1, wf: int = 5, NU=None, alpha_x=None, alpha_y=None, overlaps=None,
-                 elem_params=None):
+                 elem_params=None, local_solve: str = "mean"):
         """overlaps: optional explicit n_o per level (index 0 unused).
         elem_params: optional (alpha_e, rho_e), two (ny, nx) arrays of per-
         element width scales and overlap ratios; every level l > 0 then uses
-        ElementwiseSchwarzLevel with n_o,e = element_overlap(rho_e, p_l)."""
+        ElementwiseSchwarzLevel with n_o,e = element_overlap(rho_e, p_l).
+        local_solve: "mean" (Section 4: A_ss^{-1} / nu_bar_s) or "separable"
+        (variable nu only: SeparableSchwarzLevel, nu fitted per subdomain as
+        a(x) b(y) on the level's own nodal nu)."""
         self.orders = level_orders(p)
         self.L = len(self.orders) - 1
         self.bc = bc
@@ -128,6 +132,14 @@ class Multigrid:
                 self.elem_no.append(no)
                 self.overlaps[l] = int(no.max())
                 self.schwarz.append(ElementwiseSchwarzLevel(self.spaces[l], no, alpha_e, wf))
+        elif local_solve == "separable":
+            if NU is None:
+                raise ValueError("separable local solves need a variable nu")
+            self.schwarz = [None] + [
+                SeparableSchwarzLevel(self.spaces[l], self.overlaps[l], wf, self.NU[l])
+                for l in range(1, self.L + 1)]
+        elif local_solve != "mean":
+            raise ValueError("local_solve must be 'mean' or 'separable'")
         elif wf == WF_MULT:
             self.schwarz = [None] + [MultiplicativeSchwarzLevel(self.spaces[l], self.overlaps[l])
                                      for l in range(1, self.L + 1)]

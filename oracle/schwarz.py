@@ -129,7 +129,11 @@ class SchwarzLevel:
                    for e in range(ay.n)]
         if wf == WF_ARITH:
             self.count = counting_matrix(self)
-        # group subdomains by their local matrices; one dense inverse per group
+        self._local_solvers()
+
+    def _local_solvers(self):
+        """Groups subdomains by their local matrices; one dense inverse per group."""
+        ax, ay = self.space.ax, self.space.ay
         groups = {}
         for ey in range(ay.n):
             for ex in range(ax.n):
@@ -286,3 +290,122 @@ class MultiplicativeSchwarzLevel:
                 U[np.ix_(sy.glob, sx.glob)] += d
             U = sp.zero_boundary(U)
         return U
+
+
+def window_nodes(axis: Axis, e: int, n_o: int):
+    """Positions t of the window [e p - n_o, (e+1) p + n_o] of subdomain e that
+    are mesh nodes (with Dirichlet ends, positions beyond the boundary node
+    are not), and their global node indices.  The positions form a range."""
+    p = axis.p
+    pos, glob = [], []
+    for t in range(p + 1 + 2 * n_o):
+        g = e * p - n_o + t
+        if axis.bc == PERIODIC:
+            g %= axis.N
+        elif not 0 <= g <= axis.N - 1:
+            continue
+        pos.append(t)
+        glob.append(g)
+    return pos, glob
+
+
+def weighted_axis_matrices(axis: Axis, e: int, n_o: int, coef) -> tuple:
+    """1-D stiffness and lumped mass around subdomain e with a coefficient
+    given per window position, assembled over the elements e - 1, e, e + 1
+    (clipped at Dirichlet ends, wrapped when periodic) by GLL quadrature:
+        L^E_ab = (2/h) sum_q w_q c_q D_qa D_qb,   M^E_aa = (h/2) w_a c_a,
+    where local node q of element e + d sits at window position d p + q + n_o
+    and c_q = coef(that position clamped to the window's node range).
+    Dense N x N over all global nodes."""
+    from .gll import derivative_matrix
+    p = axis.p
+    w = axis.w
+    D = derivative_matrix(axis.xi)
+    pos, _ = window_nodes(axis, e, n_o)
+    L = np.zeros((axis.N, axis.N))
+    M = np.zeros((axis.N, axis.N))
+    for d in (-1, 0, 1):
+        E = e + d
+        if axis.bc == PERIODIC:
+            E %= axis.n
+        elif not 0 <= E < axis.n:
+            continue
+        idx = [axis.node_index(E, q) for q in range(p + 1)]
+        c = np.array([coef(min(max(d * p + q + n_o, pos[0]), pos[-1])) for q in range(p + 1)])
+        Le = (2.0 / axis.h[E]) * (D.T @ ((w * c)[:, None] * D))
+        for qa in range(p + 1):
+            M[idx[qa], idx[qa]] += 0.5 * axis.h[E] * w[qa] * c[qa]
+            for qb in range(p + 1):
+                L[idx[qa], idx[qb]] += Le[qa, qb]
+    return L, M
+
+
+def separable_fit(LG: np.ndarray):
+    """Least-squares split of a grid function into a function of the column
+    plus a function of the row, LG[j, i] ~ alpha_i + beta_j, with every grid
+    point weighted equally: alpha_i = (column mean)_i - (grand mean),
+    beta_j = (row mean)_j."""
+    g = LG.mean()
+    return LG.mean(axis=0) - g, LG.mean(axis=1)
+
+
+class SeparableSchwarzLevel(SchwarzLevel):
+    """Weighted additive Schwarz for variable diffusion with separable local
+    coefficients (a project extension; Section 4 replaces nu by its element
+    mean in the local problems, which fails where nu varies strongly inside a
+    subdomain).  For subdomain s, log nu on the window's nodes is fitted by
+    least squares as alpha(x) + beta(y) (separable_fit), and the local
+    operator is the restriction of B(nu_s) with nu_s = a(x) b(y),
+    a = exp(alpha), b = exp(beta), extended beyond the window (into the parts
+    of the neighbouring elements that the window does not cover) by the value
+    at the window's nearest node.  That operator is exactly separable,
+
+        A_s = R_s [M_b (x) L_a + L_b (x) M_a] R_s^T,
+
+    with L_a, M_a the 1-D stiffness and mass weighted by a (GLL quadrature;
+    weighted_axis_matrices), so the fast diagonalisation still applies, with
+    factors per subdomain.  Subdomains, weights and the update are the
+    paper's (Algorithm 2); there is no 1/nu_bar scaling.  Periodic
+    directions need at least 3 elements (the window then meets each
+    neighbouring element at one end only)."""
+
+    def __init__(self, space: Space, n_o: int, wf: int, NU):
+        self.NU = np.asarray(NU, dtype=np.float64)
+        for ax_ in (space.ax, space.ay):
+            if ax_.bc == PERIODIC and ax_.n < 3:
+                raise ValueError("separable local solves need 3 elements per periodic direction")
+        super().__init__(space, n_o, wf)
+
+    def coefficients(self, ey: int, ex: int):
+        """(a, b): dicts from window position to the fitted factors."""
+        ax, ay = self.space.ax, self.space.ay
+        px, gx = window_nodes(ax, ex, self.n_o)
+        py, gy = window_nodes(ay, ey, self.n_o)
+        alpha, beta = separable_fit(np.log(self.NU[np.ix_(gy, gx)]))
+        return dict(zip(px, np.exp(alpha))), dict(zip(py, np.exp(beta)))
+
+    def local_matrix_of(self, ey: int, ex: int) -> np.ndarray:
+        ax, ay = self.space.ax, self.space.ay
+        a, b = self.coefficients(ey, ex)
+        La, Ma = weighted_axis_matrices(ax, ex, self.n_o, a.__getitem__)
+        Lb, Mb = weighted_axis_matrices(ay, ey, self.n_o, b.__getitem__)
+        ix, iy = self.sx[ex].glob, self.sy[ey].glob
+        return (np.kron(Mb[np.ix_(iy, iy)], La[np.ix_(ix, ix)])
+                + np.kron(Lb[np.ix_(iy, iy)], Ma[np.ix_(ix, ix)]))
+
+    def _local_solvers(self):
+        self.inv = {}
+        for ey in range(self.space.ay.n):
+            for ex in range(self.space.ax.n):
+                self.inv[ey, ex] = np.linalg.inv(self.local_matrix_of(ey, ex))
+
+    def corrections(self, R: np.ndarray, nubar=None) -> np.ndarray:
+        """sum_s R_s^T W_s A_s^{-1} R_s r (nubar is not used: the coefficient
+        is inside A_s)."""
+        dU = np.zeros(self.space.shape)
+        for (ey, ex), Ainv in self.inv.items():
+            sy, sx = self.sy[ey], self.sx[ex]
+            Rs = R[np.ix_(sy.glob, sx.glob)]
+            d = (Ainv @ Rs.ravel()).reshape(Rs.shape)
+            dU[np.ix_(sy.glob, sx.glob)] += self.subdomain_weights(ey, ex) * d
+        return dU

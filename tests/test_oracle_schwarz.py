@@ -383,3 +383,125 @@ def test_multiplicative_even_sweeps_are_symmetric(bc, n_o):
     # and the smoother contracts in the energy norm
     lam = np.linalg.eigvals(E2)
     assert np.max(np.abs(lam)) < 1.0 + 1e-12
+
+
+# ---- separable local coefficients (variable-diffusion extension) --------------
+
+def test_separable_fit_is_least_squares():
+    """separable_fit against a generic least-squares solve of the additive
+    model alpha_i + beta_j (design matrix, lstsq)."""
+    from oracle.schwarz import separable_fit
+    rng = np.random.default_rng(3)
+    LG = rng.normal(size=(5, 7))
+    alpha, beta = separable_fit(LG)
+    ny, nx = LG.shape
+    A = np.zeros((nx * ny, nx + ny))
+    for j in range(ny):
+        for i in range(nx):
+            A[j * nx + i, i] = 1.0
+            A[j * nx + i, nx + j] = 1.0
+    c, *_ = np.linalg.lstsq(A, LG.ravel(), rcond=None)
+    fit_ls = (A @ c).reshape(ny, nx)
+    assert np.allclose(alpha[None, :] + beta[:, None], fit_ls, atol=1e-13)
+    # exact on an additive grid function
+    a0, b0 = rng.normal(size=nx), rng.normal(size=ny)
+    al, be = separable_fit(a0[None, :] + b0[:, None])
+    assert np.allclose(al[None, :] + be[:, None], a0[None, :] + b0[:, None], atol=1e-13)
+
+
+@pytest.mark.parametrize("bc,n_o", [(DIRICHLET, 0), (DIRICHLET, 1), (DIRICHLET, 3),
+                                    (PERIODIC, 1), (PERIODIC, 2)])
+def test_separable_local_matrix_is_submatrix_of_B(bc, n_o):
+    """For nu(x, y) = a(x) b(y) with a and b constant beyond the subdomain's
+    window (so that the fit and its extension reproduce nu on every element
+    the window reaches), the separable local operator equals the principal
+    submatrix of the assembled B(nu) on the subdomain's unknowns."""
+    from oracle.schwarz import SeparableSchwarzLevel, window_nodes
+    p = 4
+    xb = W.geometric_breaks(4, 0.3, 2.5)
+    # four elements along y as well: with three periodic elements the two
+    # neighbours of an element share a node, which then carries two clamped
+    # values (one per element), and no nodal nu reproduces both
+    yb = W.geometric_breaks(4, 0.4, 1.7)
+    sp = Space(xb, yb, p, bc)
+    x, y = sp.x(), sp.y()
+    num = -np.ones(sp.shape, dtype=np.int64)
+    num[sp.mask] = np.arange(int(sp.mask.sum()))
+
+    class Lazy(SeparableSchwarzLevel):
+        def _local_solvers(self):
+            pass
+
+    for ey, ex in [(0, 0), (1, 2), (3, 3), (2, 1)]:
+        px, gx = window_nodes(sp.ax, ex, n_o)
+        py, gy = window_nodes(sp.ay, ey, n_o)
+        xw, yw = x[gx], y[gy]
+        # a, b smooth inside the window, frozen at the window's end values outside
+        ax_ = 1.0 + 0.5 * np.sin(3.0 * xw) ** 2 + xw
+        by_ = np.exp(yw - yw ** 2)
+        a_node = np.empty(sp.shape[1])
+        b_node = np.empty(sp.shape[0])
+        # every node: the value at the nearest window node along the axis
+        # (window order = position order, which wraps for periodic meshes)
+        for g in range(sp.shape[1]):
+            a_node[g] = ax_[np.argmin([_axis_dist(sp.ax, g, h) for h in gx])]
+        for g in range(sp.shape[0]):
+            b_node[g] = by_[np.argmin([_axis_dist(sp.ay, g, h) for h in gy])]
+        NU = b_node[:, None] * a_node[None, :]
+        lev = Lazy(sp, n_o, 5, NU)
+        A_s = lev.local_matrix_of(ey, ex)
+        B = sp.dense_B(NU)
+        sy, sx = lev.sy[ey], lev.sx[ex]
+        ids = num[np.ix_(sy.glob, sx.glob)].ravel()
+        ref = B[np.ix_(ids, ids)]
+        assert np.abs(A_s - ref).max() <= 1e-12 * np.abs(ref).max(), (ey, ex)
+
+
+def _axis_dist(axis, g, h):
+    d = abs(g - h)
+    return min(d, axis.N - d) if axis.bc == PERIODIC else d
+
+
+def test_separable_constant_nu_is_the_paper_scaled():
+    """Constant nu = c: the separable local solves are the paper's solves
+    divided by nu_bar = c (Algorithm 2 with Section 4's scaling)."""
+    from oracle.schwarz import SeparableSchwarzLevel
+    xb = W.geometric_breaks(4, 0.3, 2.0)
+    yb = W.uniform_breaks(3, 1.0)
+    sp = Space(xb, yb, 6, DIRICHLET)
+    c = 2.75
+    sep = SeparableSchwarzLevel(sp, 2, 5, np.full(sp.shape, c))
+    ref = SchwarzLevel(sp, 2, 5)
+    R = sp.zero_boundary(W.random_nodal(sp.shape, DIRICHLET, 7))
+    nubar = np.full((3, 4), c)
+    assert np.allclose(sep.corrections(R), ref.corrections(R, nubar), rtol=0, atol=1e-13 * np.abs(R).max())
+
+
+def test_separable_local_solves_converge_where_the_mean_breaks_down():
+    """nu = exp(g) with correlation length 0.1 on the widest stretched
+    elements of the variable-diffusion workload mesh (4 x 3 elements, p = 6):
+    MGCG(1,1) with Section 4's element-mean local solves breaks down (non-
+    finite iterate), with separable local coefficients it converges."""
+    import warnings
+    from oracle.mgcg import mgcg
+    from oracle.multigrid import Multigrid, smoothing_schedule
+    cfg = W.config("c4")
+    xb, yb = cfg.xb[28:], cfg.yb[:4]
+    top = Space(xb, yb, 6, DIRICHLET)
+    NU = W.nodal(W.GaussianFieldNu(ell=0.1).nu, top.x(), top.y())
+    F = top.mass(W.random_nodal(top.shape, DIRICHLET, W.SEED_RHS))
+    U0 = W.random_guess(top.shape, DIRICHLET, W.SEED_U0)
+    res = {}
+    for ls in ("mean", "separable"):
+        mg = Multigrid(xb, yb, 6, DIRICHLET, 1, 0, 5, NU=NU, local_solve=ls)
+        ns1, ns2 = smoothing_schedule(mg.L, "mg11")
+        try:
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                _, hist, it = mgcg(mg, U0, F, 30, 1e-10, ns1, ns2)
+            res[ls] = (it, hist[-1] / hist[0])
+        except (ValueError, FloatingPointError, np.linalg.LinAlgError):
+            res[ls] = (None, np.inf)
+    assert not (res["mean"][1] <= 1e-3), res
+    it, red = res["separable"]
+    assert it is not None and red <= 1e-10 and it <= 20, res
