@@ -81,11 +81,20 @@ RULES = {"fixed": 0, "ceil8": 1, "floor8": 2, "ceil2": 3}
 PRECISIONS = ("fp64", "mixed", "bf16", "fp16")
 
 
+def progress(msg: str):
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def make_problem(name: str, precision: str = "fp64", n_o: int = 1, rule=None, overlaps=None,
-                 net=None, learned_mode: str = "level"):
+                 net=None, learned_mode: str = "level", ell=None, local: str = "mean",
+                 wf: int = 5):
     """Solver, right-hand side, nodal source, initial guess and nu of a
     workload; with a trained network `net` the Schwarz parameters are the
-    learned ones (the paper's when the prediction is unusable)."""
+    learned ones (the paper's when the prediction is unusable).  ell: the
+    random field's correlation length instead of the workload's; local:
+    "mean" (the paper's local solves) or "separable" (separable local
+    coefficients); wf: the weight function (-3: multiplicative Schwarz)."""
     import torch
     from paper_1512_02390_amd import sem as S
     from paper_1512_02390_amd import workloads as W
@@ -99,7 +108,7 @@ def make_problem(name: str, precision: str = "fp64", n_o: int = 1, rule=None, ov
         cfg.overlaps = overlaps
     NU = None
     if cfg.variable_nu:
-        nu = W.GaussianFieldNu()
+        nu = W.GaussianFieldNu() if ell is None else W.GaussianFieldNu(ell=ell)
         probe = S.Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5)
         xc, yc = probe.node_coords()
         probe.close()
@@ -110,8 +119,9 @@ def make_problem(name: str, precision: str = "fp64", n_o: int = 1, rule=None, ov
         s, learned_params = LW.solver_with_learned(cfg.xb, cfg.yb, cfg.p, cfg.bc, NU, net, prec,
                                                    learned_mode)
     else:
-        s = S.Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, 5, nu=NU,
-                     precision=prec, overlaps=cfg.overlaps)
+        s = S.Solver(cfg.xb, cfg.yb, cfg.p, cfg.bc, cfg.overlap_rule, cfg.n_o, wf, nu=NU,
+                     precision=prec, overlaps=cfg.overlaps,
+                     local_solve=S.LOCAL_SEPARABLE if local == "separable" else S.LOCAL_MEAN)
     s.learned_params = learned_params
     shape = s.shape()
     if name == "c1":
@@ -291,18 +301,38 @@ def cpu_baseline(cfg, fn, NU, ns1, ns2, budget_s: float = 15.0):
 
 
 def compare_run(name: str, precision: str, net, steps: int, warmup: int, imax: int,
-                plain_ms=None, learned_mode: str = "level"):
+                plain_ms=None, learned_mode: str = "level", ell=None, local: str = "mean",
+                wf: int = 5):
     """One comparison entry: time to 1e-10, iterations and the true FP64
-    residual of a solve configuration."""
-    cfg, s, b, u0, _, _ = make_problem(name, precision, net=net, learned_mode=learned_mode)
+    residual of a solve configuration (or the breakdown, when the iteration
+    meets a non-finite residual)."""
+    from paper_1512_02390_amd.sem import SemError
+    progress(f"comparison {name} {precision} {'learned ' + learned_mode if net is not None else 'paper'}"
+             f" local={local} wf={wf}" + (f" length={ell}" if ell is not None else ""))
+    t0 = time.perf_counter()
+    cfg, s, b, u0, _, _ = make_problem(name, precision, net=net, learned_mode=learned_mode,
+                                       ell=ell, local=local, wf=wf)
+    setup_s = time.perf_counter() - t0
     cycle, ns1, ns2 = schedule(cfg, s.L)
-    res = timed_solves(s, b, u0, steps, warmup, ns1, ns2, imax)
     entry = {"workload": cfg.description, "precision": precision,
              "weights": "learned" if net is not None else "paper", "solver": f"MGCG {cycle}",
-             "overlap": [s.level_info(l)[1] for l in range(1, s.L + 1)],
-             "time_to_1e-10_ms": 1e3 * res["s_per_solve"] if res["converged"] else None,
-             "iterations": res["iterations"], "converged": res["converged"],
-             "true_residual_ratio": true_residual_ratio(s, res["u"], b, u0)}
+             "smoother": "multiplicative" if wf == -3 else f"additive w_{wf}",
+             "local_solve": local, "setup_s": setup_s,
+             "overlap": [s.level_info(l)[1] for l in range(1, s.L + 1)]}
+    if ell is not None:
+        entry["correlation_length"] = ell
+    try:
+        res = timed_solves(s, b, u0, steps, warmup, ns1, ns2, imax)
+    except SemError as e:
+        if e.status != -6:
+            raise
+        entry.update({"time_to_1e-10_ms": None, "converged": False,
+                      "breakdown": "non-finite residual"})
+        s.close()
+        return entry
+    entry.update({"time_to_1e-10_ms": 1e3 * res["s_per_solve"] if res["converged"] else None,
+                  "iterations": res["iterations"], "converged": res["converged"],
+                  "true_residual_ratio": true_residual_ratio(s, res["u"], b, u0)})
     if net is not None:
         entry["learned_mode"] = learned_mode
         entry["learned_fallback_to_paper"] = s.learned_params is None
@@ -378,8 +408,10 @@ def main():
 
     if args.weights == "learned":
         net, learned_info = train()
+    progress(f"workload {args.workload} {args.precision}: set-up")
     cfg, s, b, u0, fn, NU = make_problem(args.workload, args.precision, args.n_o, args.rule, ovl,
                                          net)
+    progress("timed solves")
     cycle, ns1, ns2 = schedule(cfg, s.L, args.cycle)
     n_dof = n_unknowns(cfg)
 
@@ -462,14 +494,30 @@ def main():
         cmp["c3_fp16_paper"] = compare_run("c3", "fp16", None, 10, 2, args.imax, plain["c3"])
         cmp["c5_fp16_paper"] = compare_run("c5", "fp16", None, 10, 2, args.imax, plain["c5"])
         if net is None:
+            progress("training the parameter network")
             net, learned_info = train()
             cmp["learned_training"] = learned_info
         cmp["c5_fp64_learned"] = compare_run("c5", "fp64", net, 10, 2, args.imax, plain["c5"])
         cmp["c5_fp16_learned"] = compare_run("c5", "fp16", net, 10, 2, args.imax, plain["c5"])
         cmp["c5_fp16_learned_per_element"] = compare_run("c5", "fp16", net, 10, 2, args.imax,
                                                          plain["c5"], "element")
+        # variable nu with correlation length 0.1: the paper's element-mean
+        # local solves against separable local coefficients; and the separable
+        # ones on the p = 32 workload itself
+        cmp["c4_len0.1_fp64_paper"] = compare_run("c4", "fp64", None, 5, 1, args.imax, ell=0.1)
+        cmp["c4_len0.1_fp64_separable"] = compare_run("c4", "fp64", None, 10, 2, args.imax,
+                                                      ell=0.1, local="separable")
+        cmp["c5_fp64_separable"] = compare_run("c5", "fp64", None, 10, 2, args.imax, plain["c5"],
+                                               local="separable")
+        # Algorithm 1 (sequential sweeps in one workgroup) against the additive
+        # smoother on the 64 x 64, p = 8 workload
+        cmp["c2_fp64_paper"] = compare_run("c2", "fp64", None, 10, 2, args.imax)
+        cmp["c2_fp64_multiplicative"] = compare_run("c2", "fp64", None, 2, 1, args.imax,
+                                                    cmp["c2_fp64_paper"]["time_to_1e-10_ms"],
+                                                    wf=-3)
         out["comparisons"] = cmp
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, fn, NU, ns1, ns2)
     print(json.dumps(out), flush=True)
 

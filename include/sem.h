@@ -47,7 +47,20 @@ typedef enum { SEM_BC_DIRICHLET = 0, SEM_BC_PERIODIC = 1 } sem_bc;
 /* Weight functions of Table 1 (Section 3.1).  Odd kappa >= 1 selects the
  * smoothed sign function of that order (1 linear, 3 cubic, 5 quintic,
  * 7 seventh order, larger odd orders by the same defining conditions). */
-typedef enum { SEM_W_TOPHAT = -1, SEM_W_ARITH = -2 } sem_wf_special;
+/* SEM_W_MULT selects the multiplicative Schwarz method of Algorithm 1
+ * instead: the subdomain problems are solved one after the other in
+ * row-major element order (reversed on every second sweep), each on the
+ * residual left by the corrections before it, without weights.  It is
+ * sequential, so one workgroup runs it; supported for the Poisson operator
+ * (nu = NULL) in SEM_FP64 precision, without width scales or per-element
+ * parameters (SEM_EUNSUP otherwise). */
+typedef enum { SEM_W_TOPHAT = -1, SEM_W_ARITH = -2, SEM_W_MULT = -3 } sem_wf_special;
+
+/* Local subdomain problems for variable nu (sem_weights.local_solve). */
+typedef enum {
+  SEM_LOCAL_MEAN = 0,      /* Section 4: A_ss^{-1} r_s / nu_bar_s (element mean) */
+  SEM_LOCAL_SEPARABLE = 1  /* separable fit of nu per subdomain (extension)      */
+} sem_local_solve;
 
 /* Overlap n_o per multigrid level l > 0 (Section 4); always clamped to
  * [0, p_l - 1]. */
@@ -110,6 +123,21 @@ typedef struct {
    * When non-NULL, alpha_x / alpha_y must be NULL and the overlap rule is
    * not used on levels l > 0 (sem_level_info reports the largest n_o,e). */
   const float *elem_params;
+  /* sem_local_solve (a project extension; 0 is the paper's method).  With
+   * SEM_LOCAL_SEPARABLE (variable nu only, not with elem_params), each
+   * subdomain s of level l > 0 fits log nu on its window's nodes (level l's
+   * nodal nu) by least squares as alpha(x) + beta(y): alpha = column means
+   * minus the grand mean, beta = row means.  Its local operator is the
+   * restriction of B(a(x) b(y)), a = exp(alpha), b = exp(beta), extended
+   * beyond the window by the value at its nearest node:
+   *   A_s = M_b (x) L_a + L_b (x) M_a,
+   * with L_a, M_a the 1-D stiffness and lumped mass weighted by a (GLL
+   * quadrature over the elements the window reaches).  It is separable, so
+   * the fast diagonalisation applies with one factor pair per subdomain
+   * (host set-up cost and factor memory grow with the element count); no
+   * 1/nu_bar scaling.  Subdomains, weights and the update stay the paper's.
+   * For nu = a(x) b(y) the fit is exact inside each window. */
+  int32_t local_solve;
 } sem_weights;
 
 /* Build all levels, operators, fast-diagonalisation factors, weights,

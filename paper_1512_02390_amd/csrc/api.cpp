@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include <stdexcept>
 #include <string>
 #include <type_traits>
+#include <thread>
 #include <vector>
 
 #include "../../include/sem.h"
@@ -75,6 +77,87 @@ T *dalloc(std::vector<std::unique_ptr<DBuf>> &pool, size_t n) {
   return pool.back()->as<T>();
 }
 
+// Copies a host array of any trivially copyable type to a new device buffer.
+template <typename T>
+T *upload_raw(std::vector<std::unique_ptr<DBuf>> &pool, const std::vector<T> &h) {
+  pool.emplace_back(new DBuf());
+  DBuf &b = *pool.back();
+  b.alloc(h.size() * sizeof(T));
+  if (h.empty()) return nullptr;
+  HIP_OK(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return b.as<T>();
+}
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+uint16_t f16_bits(float x) {
+  const _Float16 h = (_Float16)x;   // round to nearest even
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+// Matrix-core B operands of one direction's subdomain types (MfmaOps):
+// B(t, q, k, n) is entry (k, n) of matrix q in {0, 1} of type t.  Values
+// are laid out [t][q][KC][NB][lane][8] with the permuted k order of the
+// kernel, scaled by 2^-e per matrix (FP16; e = 0 for BF16).
+template <typename F>
+void mfma_operands(const F &B, int ntypes, int m, bool fp16, std::vector<uint16_t> &vals,
+                   std::vector<int32_t> &exps) {
+  const int NB = (m + 15) / 16, KC = (NB + 1) / 2;
+  vals.assign((size_t)ntypes * 2 * KC * NB * 64 * 8, 0);
+  exps.assign((size_t)ntypes * 2, 0);
+  for (int t = 0; t < ntypes; ++t)
+    for (int q = 0; q < 2; ++q) {
+      int e = 0;
+      if (fp16) {
+        double amax = 0.0;
+        for (int k = 0; k < m; ++k)
+          for (int n = 0; n < m; ++n) amax = std::max(amax, std::fabs(B(t, q, k, n)));
+        if (amax > 0.0) std::frexp(amax, &e);   // amax = f 2^e, f in [0.5, 1)
+      }
+      exps[(size_t)t * 2 + q] = e;
+      const double sc = std::ldexp(1.0, -e);
+      for (int c = 0; c < KC; ++c)
+        for (int J = 0; J < NB; ++J)
+          for (int l = 0; l < 64; ++l)
+            for (int v = 0; v < 8; ++v) {
+              const int g = l / 16;
+              const int k = 32 * c + (v < 4 ? 4 * g + v : 16 + 4 * g + v - 4);
+              const int n = 16 * J + l % 16;
+              const float x = (k < m && n < m) ? (float)(B(t, q, k, n) * sc) : 0.f;
+              vals[((((size_t)t * 2 + q) * KC + c) * NB + J) * 512 + (size_t)l * 8 + v] =
+                  fp16 ? f16_bits(x) : bf16_bits(x);
+            }
+    }
+}
+
+// MfmaOps of a set of subdomain types: y types from S_y^T and diag(w_y) S_y
+// (B = S_y and (W_y S_y)^T), x types from S_x (B = S_x and S_x^T).
+MfmaOps build_mfma_ops(std::vector<std::unique_ptr<DBuf>> &pool, const std::vector<double> &SyT, const std::vector<double> &SyW,
+                       int nty, const std::vector<double> &Sx, int ntx, int m, bool fp16) {
+  const size_t mm = (size_t)m * m;
+  std::vector<uint16_t> vy, vx;
+  std::vector<int32_t> ey, ex;
+  mfma_operands([&](int t, int q, int k, int n) {
+    return (q == 0 ? SyT : SyW)[t * mm + (size_t)n * m + k];
+  }, nty, m, fp16, vy, ey);
+  mfma_operands([&](int t, int q, int k, int n) {
+    return q == 0 ? Sx[t * mm + (size_t)k * m + n] : Sx[t * mm + (size_t)n * m + k];
+  }, ntx, m, fp16, vx, ex);
+  MfmaOps mo;
+  mo.by = reinterpret_cast<const uint4 *>(upload_raw<uint16_t>(pool, vy));
+  mo.bx = reinterpret_cast<const uint4 *>(upload_raw<uint16_t>(pool, vx));
+  mo.ey = upload_raw<int32_t>(pool, ey);
+  mo.ex = upload_raw<int32_t>(pool, ex);
+  return mo;
+}
+
 // Tables of one level in one precision.
 template <typename T>
 struct Tables {
@@ -106,6 +189,7 @@ struct Seg {
   FdmTask *tasks = nullptr;
   FdmTab<double> d;
   FdmTab<float> f;
+  MfmaOps mo;   // matrix-core operands (BF16 / FP16 precision, m >= kMfmaMinTile)
 };
 
 struct Level {
@@ -120,6 +204,8 @@ struct Level {
   Tables<float> tf;
   FdmTask *tasks = nullptr;
   int ntasks = 0, ntx = 0, nty = 0;
+  MfmaOps mo;   // matrix-core operands (BF16 / FP16 precision, m >= kMfmaMinTile)
+  int32_t *tx_of = nullptr, *ty_of = nullptr;   // subdomain type per element column / row
   // level vectors (FP64 and FP32)
   double *u = nullptr, *f = nullptr, *r = nullptr;
   float *uf = nullptr, *ff = nullptr, *rf = nullptr;
@@ -132,6 +218,7 @@ struct sem_ctx {
   hipStream_t stream = nullptr;
   int precision = SEM_FP64;
   int bc = SEM_BC_DIRICHLET;
+  bool mult = false;   // multiplicative Schwarz (SEM_W_MULT) on levels l > 0
   bool varnu = false;
   std::vector<Level> lev;
   std::vector<std::unique_ptr<DBuf>> pool;
@@ -467,6 +554,7 @@ void build_segments(sem_ctx *h, Level &lv, const std::vector<double> &xb,
                     const std::vector<double> &yb, int per, int wf, const float *ep, bool mixed) {
   const int nx = lv.g.nx, ny = lv.g.ny, p = lv.p;
   const long ne = (long)nx * ny;
+  const bool mfma = h->precision == SEM_MIXED_BF16 || h->precision == SEM_MIXED_FP16;
   std::vector<int> no(ne);
   for (long e = 0; e < ne; ++e) no[e] = element_overlap(ep[2 * e + 1], p);
   std::vector<int> vals(no.begin(), no.end());
@@ -555,12 +643,199 @@ void build_segments(sem_ctx *h, Level &lv, const std::vector<double> &xb,
     };
     fill(sg.d, double());
     if (mixed) fill(sg.f, float());
+    if (mfma && m >= kMfmaMinTile)
+      sg.mo = build_mfma_ops(h->pool, fy.ST, fy.SW, fy.ntypes, fx.S, fx.ntypes, m,
+                             h->precision == SEM_MIXED_FP16);
     lv.segs.push_back(sg);
   }
   std::vector<double> dn((size_t)R * Cc, 0.0);
   for (size_t i = 0; i < dn.size(); ++i) dn[i] = Dsum[i] > 0.0 ? 1.0 / Dsum[i] : 0.0;
   lv.dnorm = upload<double>(h->pool, dn);
   if (mixed) lv.dnormf = upload<float>(h->pool, dn);
+}
+
+// Window of subdomain e along one axis: for every position t of
+// [e p - n_o, (e+1) p + n_o], the global node (-1 beyond a Dirichlet end)
+// and whether it is an unknown; [first, last] is the range of positions
+// that are nodes.
+struct AxisWindow {
+  std::vector<int> node;
+  std::vector<char> valid;
+  int first = -1, last = -1;
+};
+
+AxisWindow axis_window(int e, int p, int n_o, int N, int per) {
+  AxisWindow w;
+  const int m = p + 1 + 2 * n_o;
+  for (int t = 0; t < m; ++t) {
+    int g = e * p - n_o + t;
+    bool exists, valid;
+    if (per) {
+      g = ((g % N) + N) % N;
+      exists = valid = true;
+    } else {
+      exists = g >= 0 && g <= N - 1;
+      valid = g >= 1 && g <= N - 2;
+    }
+    w.node.push_back(exists ? g : -1);
+    w.valid.push_back(valid);
+    if (exists) {
+      if (w.first < 0) w.first = t;
+      w.last = t;
+    }
+  }
+  return w;
+}
+
+// 1-D stiffness and lumped mass on the window of subdomain e, weighted by a
+// coefficient given per window position (coef[t], t in [first, last]):
+// GLL quadrature over the elements e - 1, e, e + 1 that exist, with local
+// node q of element e + d at position d p + q + n_o and its coefficient
+// taken at that position clamped to [first, last].
+void weighted_window_ops(const std::vector<double> &br, int e, int p, int n_o, int per,
+                         const AxisWindow &win, const Vec &coef, const Vec &w, const Mat &D,
+                         Mat &Ls, Vec &Ms) {
+  const int n = (int)br.size() - 1;
+  const int m = p + 1 + 2 * n_o;
+  Ls = Mat(m, m);
+  Ms.assign(m, 0.0);
+  Vec c(p + 1);
+  for (int d = -1; d <= 1; ++d) {
+    int E = e + d;
+    if (per)
+      E = (E + n) % n;
+    else if (E < 0 || E >= n)
+      continue;
+    const double h = br[E + 1] - br[E];
+    for (int q = 0; q <= p; ++q)
+      c[q] = coef[std::min(std::max(d * p + q + n_o, win.first), win.last)];
+    for (int a = 0; a <= p; ++a) {
+      const int ka = d * p + a + n_o;
+      if (ka < 0 || ka >= m) continue;
+      Ms[ka] += 0.5 * h * w[a] * c[a];
+      for (int b = 0; b <= p; ++b) {
+        const int kb = d * p + b + n_o;
+        if (kb < 0 || kb >= m) continue;
+        double sum = 0.0;
+        for (int r = 0; r <= p; ++r) sum += w[r] * c[r] * D(r, a) * D(r, b);
+        Ls(ka, kb) += (2.0 / h) * sum;
+      }
+    }
+  }
+}
+
+// Fast-diagonalisation factors of (Ls, Ms) on the valid positions, padded
+// with identity rows (lambda = 1) at the others: S (m x m), lambda (m).
+void padded_factors(const Mat &Ls, const Vec &Ms, const std::vector<char> &valid, Vec &Sp,
+                    Vec &lp) {
+  const int m = (int)valid.size();
+  std::vector<int> vi, ii;
+  for (int k = 0; k < m; ++k) (valid[k] ? vi : ii).push_back(k);
+  const int nv = (int)vi.size();
+  Mat L(nv, nv);
+  Vec M(nv);
+  for (int a = 0; a < nv; ++a) {
+    M[a] = Ms[vi[a]];
+    for (int b = 0; b < nv; ++b) L(a, b) = Ls(vi[a], vi[b]);
+  }
+  Vec lam;
+  Mat S;
+  gen_eig_diag(L, M, lam, S);
+  Sp.assign((size_t)m * m, 0.0);
+  lp.assign(m, 1.0);
+  for (int a = 0; a < nv; ++a) {
+    lp[a] = lam[a];
+    for (int c2 = 0; c2 < nv; ++c2) Sp[(size_t)vi[a] * m + c2] = S(a, c2);
+  }
+  for (size_t t = 0; t < ii.size(); ++t) Sp[(size_t)ii[t] * m + nv + t] = 1.0;
+}
+
+// Separable local coefficients (sem_weights.local_solve =
+// SEM_LOCAL_SEPARABLE): for subdomain e = ey nx + ex, log nu on the window's
+// nodes is fitted as alpha(x) + beta(y) by least squares (column means minus
+// the grand mean, row means); the local operator M_b (x) L_a + L_b (x) M_a
+// with a = exp(alpha), b = exp(beta) (weighted_window_ops) is diagonalised
+// per direction.  fx / fy come in from build_direction (the paper's weights)
+// and leave with one type per subdomain, type e in both directions; dinv
+// holds one eigenvalue-sum tile per subdomain (indexed by the x type, the
+// kernels' pair stride being 0), and every task holds one subdomain.
+void build_separable(const Level &lv, const std::vector<double> &xb, const std::vector<double> &yb,
+                     int per, DirFdm &fx, DirFdm &fy, std::vector<double> &dinv,
+                     std::vector<FdmTask> &tasks) {
+  const int nx = lv.g.nx, ny = lv.g.ny, p = lv.p, n_o = lv.n_o, m = lv.m;
+  const int R = lv.g.rows, Cc = lv.g.cols;
+  const long ne = (long)nx * ny;
+  Vec xi, w;
+  gll_rule(p, xi, w);
+  const Mat D = lagrange_derivative(xi);
+  std::vector<AxisWindow> wx(nx), wy(ny);
+  for (int e = 0; e < nx; ++e) wx[e] = axis_window(e, p, n_o, Cc, per);
+  for (int e = 0; e < ny; ++e) wy[e] = axis_window(e, p, n_o, R, per);
+  const size_t mm = (size_t)m * m;
+  std::vector<double> Sx(ne * mm), SxT(ne * mm), SyW(ne * mm), SyT(ne * mm), dv(ne * mm);
+  auto work = [&](long e) {
+    const int ey = (int)(e / nx), ex = (int)(e % nx);
+    const AxisWindow &ax = wx[ex], &ay = wy[ey];
+    const int nxw = ax.last - ax.first + 1, nyw = ay.last - ay.first + 1;
+    // least-squares split of log nu over the window's node grid
+    std::vector<double> lg((size_t)nyw * nxw);
+    for (int j = 0; j < nyw; ++j)
+      for (int i = 0; i < nxw; ++i)
+        lg[(size_t)j * nxw + i] =
+            std::log(lv.nu_host[(size_t)ay.node[ay.first + j] * Cc + ax.node[ax.first + i]]);
+    double grand = 0.0;
+    for (double v : lg) grand += v;
+    grand /= (double)lg.size();
+    Vec ca(m, 0.0), cb(m, 0.0);
+    for (int i = 0; i < nxw; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < nyw; ++j) s += lg[(size_t)j * nxw + i];
+      ca[ax.first + i] = std::exp(s / nyw - grand);
+    }
+    for (int j = 0; j < nyw; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < nxw; ++i) s += lg[(size_t)j * nxw + i];
+      cb[ay.first + j] = std::exp(s / nxw);
+    }
+    Mat La, Lb;
+    Vec Ma, Mb, Spx, lx, Spy, ly;
+    weighted_window_ops(xb, ex, p, n_o, per, ax, ca, w, D, La, Ma);
+    weighted_window_ops(yb, ey, p, n_o, per, ay, cb, w, D, Lb, Mb);
+    padded_factors(La, Ma, ax.valid, Spx, lx);
+    padded_factors(Lb, Mb, ay.valid, Spy, ly);
+    const double *wyv = fy.wts.data() + (size_t)ey * m;
+    for (int a = 0; a < m; ++a)
+      for (int c = 0; c < m; ++c) {
+        Sx[e * mm + (size_t)a * m + c] = Spx[(size_t)a * m + c];
+        SxT[e * mm + (size_t)a * m + c] = Spx[(size_t)c * m + a];
+        SyW[e * mm + (size_t)a * m + c] = wyv[a] * Spy[(size_t)a * m + c];
+        SyT[e * mm + (size_t)a * m + c] = Spy[(size_t)c * m + a];
+        dv[e * mm + (size_t)a * m + c] = 1.0 / (ly[a] + lx[c]);
+      }
+  };
+  // the subdomains are independent: spread them over the host's cores
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<long> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&] {
+      for (long e = next++; e < ne; e = next++) work(e);
+    });
+  for (std::thread &t : pool) t.join();
+  fx.ntypes = fy.ntypes = (int)ne;
+  fx.S = std::move(Sx);
+  fx.ST = std::move(SxT);
+  fy.SW = std::move(SyW);
+  fy.ST = std::move(SyT);
+  dinv = std::move(dv);
+  tasks.clear();
+  for (long e = 0; e < ne; ++e) {
+    FdmTask t{};
+    t.ty = t.tx = (int)e;
+    t.count = 1;
+    t.elem[0] = (int)(((e / nx) << 16) | (e % nx));
+    tasks.push_back(t);
+  }
 }
 
 void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
@@ -573,13 +848,22 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   if (mesh->bc != SEM_BC_DIRICHLET && !per) throw Fail{SEM_EINVAL, "bad boundary condition"};
   if (per && (nx < 3 || ny < 3)) throw Fail{SEM_EINVAL, "periodic needs at least 3 elements"};
   if (ov->rule == SEM_NO_FIXED && ov->n_o < 0) throw Fail{SEM_EINVAL, "n_o < 0"};
-  if (!(wts->wf == SEM_W_TOPHAT || wts->wf == SEM_W_ARITH || (wts->wf >= 1 && wts->wf % 2 == 1)))
-    throw Fail{SEM_EINVAL, "weight function must be odd kappa, top hat or arithmetic"};
+  if (!(wts->wf == SEM_W_TOPHAT || wts->wf == SEM_W_ARITH || wts->wf == SEM_W_MULT ||
+        (wts->wf >= 1 && wts->wf % 2 == 1)))
+    throw Fail{SEM_EINVAL, "weight function must be odd kappa, top hat, arithmetic or multiplicative"};
+  if (wts->wf == SEM_W_MULT &&
+      (nu || h->precision != SEM_FP64 || wts->alpha_x || wts->alpha_y || wts->elem_params ||
+       wts->local_solve != SEM_LOCAL_MEAN))
+    throw Fail{SEM_EUNSUP, "multiplicative Schwarz: Poisson, FP64, paper weights only"};
   std::vector<double> xb(mesh->xb, mesh->xb + nx + 1), yb(mesh->yb, mesh->yb + ny + 1);
   for (int i = 0; i < nx; ++i)
     if (!(xb[i + 1] > xb[i])) throw Fail{SEM_EDOM, "x breaks not increasing"};
   for (int i = 0; i < ny; ++i)
     if (!(yb[i + 1] > yb[i])) throw Fail{SEM_EDOM, "y breaks not increasing"};
+  if (wts->local_solve != SEM_LOCAL_MEAN && wts->local_solve != SEM_LOCAL_SEPARABLE)
+    throw Fail{SEM_EINVAL, "unknown local solve"};
+  if (wts->local_solve == SEM_LOCAL_SEPARABLE && (!nu || wts->elem_params))
+    throw Fail{SEM_EINVAL, "separable local solves need nu and exclude per-element parameters"};
   if (wts->elem_params) {
     if (wts->alpha_x || wts->alpha_y)
       throw Fail{SEM_EINVAL, "per-element parameters exclude per-line width scales"};
@@ -597,6 +881,7 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
   }
   h->bc = mesh->bc;
   h->varnu = nu != nullptr;
+  h->mult = wts->wf == SEM_W_MULT;
   {
     std::vector<double> wx(nx), wy(ny);
     for (int e = 0; e < nx; ++e) wx[e] = xb[e + 1] - xb[e];
@@ -672,24 +957,32 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
       gll_rule(lv.p, xi, w);
       Mat E = lagrange_eval(xiL, xi);  // (p_l+1) x (p_L+1)
       lv.nu_host.assign(lv.n(), 0.0);
+      // element by element, sum-factorised: along x first (T), then along y
+      std::vector<double> T((size_t)(top.p + 1) * (lv.p + 1));
       for (int ey = 0; ey < ny; ++ey)
-        for (int ex = 0; ex < nx; ++ex)
+        for (int ex = 0; ex < nx; ++ex) {
+          for (int d = 0; d <= top.p; ++d) {
+            int row = ey * top.p + d;
+            if (per) row %= top.g.rows;
+            for (int a = 0; a <= lv.p; ++a) {
+              double t = 0.0;
+              for (int c = 0; c <= top.p; ++c) {
+                int col = ex * top.p + c;
+                if (per) col %= top.g.cols;
+                t += E(a, c) * top.nu_host[(size_t)row * top.g.cols + col];
+              }
+              T[(size_t)d * (lv.p + 1) + a] = t;
+            }
+          }
           for (int b = 0; b <= lv.p; ++b)
             for (int a = 0; a <= lv.p; ++a) {
               double s = 0.0;
-              for (int d = 0; d <= top.p; ++d) {
-                double t = 0.0;
-                for (int c = 0; c <= top.p; ++c) {
-                  int row = ey * top.p + d, col = ex * top.p + c;
-                  if (per) { row %= top.g.rows; col %= top.g.cols; }
-                  t += E(a, c) * top.nu_host[(size_t)row * top.g.cols + col];
-                }
-                s += E(b, d) * t;
-              }
+              for (int d = 0; d <= top.p; ++d) s += E(b, d) * T[(size_t)d * (lv.p + 1) + a];
               int row = ey * lv.p + b, col = ex * lv.p + a;
               if (per) { row %= lv.g.rows; col %= lv.g.cols; }
               lv.nu_host[(size_t)row * lv.g.cols + col] = s;
             }
+        }
     }
   }
   std::vector<double> nuinv;
@@ -716,29 +1009,45 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     DirFdm fx, fy;
     std::vector<double> dinv;
     const bool single = l > 0 && !wts->elem_params;
+    const bool separable = single && wts->local_solve == SEM_LOCAL_SEPARABLE;
     if (l > 0 && wts->elem_params)
       build_segments(h, lv, xb, yb, per, wts->wf, wts->elem_params, mixed);
     if (single) {
-      fx = build_direction(xb, lv.p, lv.n_o, per, wts->wf, wts->alpha_x);
-      fy = build_direction(yb, lv.p, lv.n_o, per, wts->wf, wts->alpha_y);
+      // (the multiplicative method uses no weights: unit weights)
+      fx = build_direction(xb, lv.p, lv.n_o, per, wts->wf, wts->alpha_x, h->mult);
+      fy = build_direction(yb, lv.p, lv.n_o, per, wts->wf, wts->alpha_y, h->mult);
+      if (h->mult) {
+        std::vector<int32_t> txo(fx.type_of.begin(), fx.type_of.end()),
+            tyo(fy.type_of.begin(), fy.type_of.end());
+        lv.tx_of = upload_raw<int32_t>(h->pool, txo);
+        lv.ty_of = upload_raw<int32_t>(h->pool, tyo);
+      }
       const int m = lv.m;
       lv.ntx = fx.ntypes;
       lv.nty = fy.ntypes;
-      dinv.resize((size_t)fy.ntypes * fx.ntypes * m * m);
-      for (int ty = 0; ty < fy.ntypes; ++ty)
-        for (int tx = 0; tx < fx.ntypes; ++tx)
-          for (int a = 0; a < m; ++a)
-            for (int c = 0; c < m; ++c)
-              dinv[(((size_t)ty * fx.ntypes + tx) * m + a) * m + c] =
-                  1.0 / (fy.lam[(size_t)ty * m + a] + fx.lam[(size_t)tx * m + c]);
-      std::vector<FdmTask> tasks = build_tasks(fx, fy, nx, ny, m);
+      std::vector<FdmTask> tasks;
+      if (separable) {
+        build_separable(lv, xb, yb, per, fx, fy, dinv, tasks);
+        lv.ntx = 0;   // pair index = x type = subdomain
+        lv.nty = fy.ntypes;
+      } else {
+        dinv.resize((size_t)fy.ntypes * fx.ntypes * m * m);
+        for (int ty = 0; ty < fy.ntypes; ++ty)
+          for (int tx = 0; tx < fx.ntypes; ++tx)
+            for (int a = 0; a < m; ++a)
+              for (int c = 0; c < m; ++c)
+                dinv[(((size_t)ty * fx.ntypes + tx) * m + a) * m + c] =
+                    1.0 / (fy.lam[(size_t)ty * m + a] + fx.lam[(size_t)tx * m + c]);
+        tasks = build_tasks(fx, fy, nx, ny, m);
+      }
       lv.ntasks = (int)tasks.size();
       h->pool.emplace_back(new DBuf());
       h->pool.back()->alloc(tasks.size() * sizeof(FdmTask));
       lv.tasks = h->pool.back()->as<FdmTask>();
       HIP_OK(hipMemcpy(lv.tasks, tasks.data(), tasks.size() * sizeof(FdmTask), hipMemcpyHostToDevice));
     }
-    const std::vector<double> &ninv = (l > 0) ? nuinv : std::vector<double>();
+    // the separable local operators carry nu themselves: no 1/nu_bar scaling
+    const std::vector<double> &ninv = (l > 0 && !separable) ? nuinv : std::vector<double>();
     std::vector<double> DTv((size_t)(lv.p + 1) * (lv.p + 1));
     for (int a = 0; a <= lv.p; ++a)
       for (int b = 0; b <= lv.p; ++b) DTv[(size_t)a * (lv.p + 1) + b] = D(b, a);
@@ -747,6 +1056,10 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     if (mixed)
       upload_tables<float>(h, lv, lv.tf, flat(Lh), flat(D), DTv, w, sx, sy, mx, my, single ? &fx : nullptr,
                            single ? &fy : nullptr, dinv, ninv, E);
+    if (single && lv.m >= kMfmaMinTile &&
+        (h->precision == SEM_MIXED_BF16 || h->precision == SEM_MIXED_FP16))
+      lv.mo = build_mfma_ops(h->pool, fy.ST, fy.SW, fy.ntypes, fx.S, fx.ntypes, lv.m,
+                             h->precision == SEM_MIXED_FP16);
     // vectors
     const long n = lv.n();
     if (l < L) {
@@ -932,19 +1245,37 @@ void fdm(sem_ctx *h, int l, const T *r, T *u) {
                    st.dinv, sg.ntx, nullptr, t.nuinv};
       a.wel = st.wel;
       a.dnorm = level_dnorm<T>(L);
+      a.mo = sg.mo;
       launch_fdm_prec<T>(h, a);
     }
     return;
   }
   FdmArgs<T> a{L.g, L.n_o, L.m, L.tasks, L.ntasks, r, u, t.Sx, t.SxT, t.SyW, t.SyT, t.dinv, L.ntx,
                t.wx, t.nuinv};
+  a.mo = L.mo;
   TimedLaunch tl(h, l, SEM_TIME_SCHWARZ);
   launch_fdm_prec<T>(h, a);
+}
+
+// n_it sweeps of Algorithm 1 on level l > 0 (SEM_W_MULT, FP64 only).
+void smooth_mult(sem_ctx *h, int l, double *u, const double *f, int n_it) {
+  Level &L = h->lev[l];
+  Tables<double> &t = L.td;
+  MultArgs a{L.g,   L.n_o,  L.m,   n_it,  f,     u,      t.Lhat, t.w,  t.sx,  t.sy,     t.mx,
+             t.my,  t.SyW,  t.SyT, t.Sx,  t.SxT, t.dinv, L.ntx,  L.tx_of, L.ty_of};
+  TimedLaunch tl(h, l, SEM_TIME_SCHWARZ);
+  launch_mult(a, h->stream);
 }
 
 // n_it sweeps of Algorithm 2; if u_is_zero the first residual is f itself.
 template <typename T>
 void smooth(sem_ctx *h, int l, T *u, const T *f, T *rbuf, int n_it, bool u_is_zero) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->mult) {
+      smooth_mult(h, l, u, f, n_it);
+      return;
+    }
+  }
   for (int it = 0; it < n_it; ++it) {
     const T *r = f;
     if (!(it == 0 && u_is_zero)) {

@@ -2,10 +2,26 @@
 #include "host_math.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <functional>
 #include <stdexcept>
+#include <thread>
+#include <vector>
 
 namespace sem {
+
+// Runs f(i) for i in [0, n) on the host's cores (at most 16 threads).
+static void parallel_for(int n, const std::function<void(int)> &f) {
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) f(i);
+    });
+  for (std::thread &t : pool) t.join();
+}
 
 // Legendre P_n and P_n' by the three-term recurrence.
 static void legendre_pd(int n, double x, double &P, double &dP) {
@@ -180,23 +196,32 @@ bool spd_inverse(Mat &A) {
       A(i, j) = t / g;
     }
   }
-  // inverse of G (lower triangular), in place
-  Mat Gi(n, n);
-  for (int j = 0; j < n; ++j) {
-    Gi(j, j) = 1.0 / A(j, j);
+  // H = G^{-1} (lower triangular), stored transposed (Ht(j, k) = H(k, j)) so
+  // that both remaining phases read contiguous rows; the columns of H, and
+  // then the rows of the product, are independent and spread over threads
+  Mat Ht(n, n);
+  parallel_for(n, [&](int j) {
+    double *hj = &Ht.a[(size_t)j * n];
+    hj[j] = 1.0 / A(j, j);
     for (int i = j + 1; i < n; ++i) {
+      const double *gi = &A.a[(size_t)i * n];
       double t = 0.0;
-      for (int k = j; k < i; ++k) t -= A(i, k) * Gi(k, j);
-      Gi(i, j) = t / A(i, i);
+      for (int k = j; k < i; ++k) t -= gi[k] * hj[k];
+      hj[i] = t / gi[i];
     }
-  }
-  // A^{-1} = G^{-T} G^{-1}
-  for (int i = 0; i < n; ++i)
+  });
+  // A^{-1}(i, j) = sum_k H(k, i) H(k, j), k >= max(i, j)
+  parallel_for(n, [&](int i) {
+    const double *hi = &Ht.a[(size_t)i * n];
     for (int j = 0; j <= i; ++j) {
+      const double *hj = &Ht.a[(size_t)j * n];
       double t = 0.0;
-      for (int k = i; k < n; ++k) t += Gi(k, i) * Gi(k, j);
-      A(i, j) = A(j, i) = t;
+      for (int k = i; k < n; ++k) t += hi[k] * hj[k];
+      A(i, j) = t;
     }
+  });
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) A(j, i) = A(i, j);
   return true;
 }
 

@@ -1,6 +1,7 @@
 // Host-side numerics for the set-up phase: GLL rules, Lagrange operators,
 // symmetric eigen-solver, dense Cholesky, and the paper's weight function.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 

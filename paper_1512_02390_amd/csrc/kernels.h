@@ -56,6 +56,21 @@ inline long residual_waves(const Grid &g) {
   return (long)((g.nx + ne - 1) / ne) * g.ny;
 }
 
+// Matrix-core operands of the reduced-precision Schwarz kernel, prepared at
+// set-up from the FP64 factors: for every subdomain type the two B-operand
+// matrices of its direction (y: S_y and (W_y S_y)^T; x: S_x and S_x^T) in
+// the lane layout of v_mfma_f32_16x16x32_{f16,bf16}, as 16-bit values
+// scaled by 2^-e (FP16: e per matrix brings its largest magnitude into
+// [0.5, 1); BF16: e = 0).  Layout [type][matrix][KC][NB][64 lanes] of 8
+// values (16 bytes) each, NB = ceil(m / 16), KC = ceil(NB / 2); the k index
+// of value s in lane l of chunk c is 32 c + 4 (l / 16) + s for s < 4 and
+// 32 c + 16 + 4 (l / 16) + s - 4 for s >= 4 (the row order in which the
+// accumulators of the previous product arrive), the n index 16 J + l % 16.
+struct MfmaOps {
+  const uint4 *by = nullptr, *bx = nullptr;
+  const int32_t *ey = nullptr, *ex = nullptr;   // [type][2] exponents e
+};
+
 template <typename T>
 struct FdmArgs {
   Grid g;
@@ -65,8 +80,9 @@ struct FdmArgs {
   const T *r;
   T *u;
   const T *Sx, *SxT, *SyW, *SyT;  // per type m*m; SyW = diag(w_y) S_y
-  const T *dinv;                  // per (ty, tx) pair m*m
-  int32_t ntx;
+  const T *dinv;                  // per (ty, tx) pair m*m, tile index ty * ntx + tx
+  int32_t ntx;                    // number of x types, or 0 when every subdomain has
+                                  // its own types (ty = tx) and its own tile
   const T *wx;                    // per x-element m weights
   const T *nuinv;                 // per element 1/nu_bar or null
   // Per-element weights (learned parameters): when non-null, element
@@ -76,7 +92,24 @@ struct FdmArgs {
   // D the sum of the subdomain weights at the node (Shepard normalisation).
   const T *wel = nullptr;
   const T *dnorm = nullptr;
+  MfmaOps mo{};                   // matrix-core operands (reduced-precision path only)
 };
+
+// Multiplicative Schwarz sweeps (Algorithm 1) of one level, Poisson, FP64:
+// n_it sweeps, alternately forward and reversed over e = ey nx + ex.
+struct MultArgs {
+  Grid g;
+  int32_t n_o, m, n_it;
+  const double *f;
+  double *u;
+  const double *Lhat, *w;          // reference stiffness, GLL weights
+  const double *sx, *sy, *mx, *my;  // per element 2/h and h/2
+  const double *Sy, *SyT, *Sx, *SxT;  // unweighted factors per type, m*m
+  const double *dinv;              // per (ty, tx) pair m*m, tile ty * ntx + tx
+  int32_t ntx;
+  const int32_t *tx_of, *ty_of;    // subdomain type per element column / row
+};
+void launch_mult(const MultArgs &a, hipStream_t s);
 
 template <typename T>
 void launch_residual(const ResidualArgs<T> &a, hipStream_t s);

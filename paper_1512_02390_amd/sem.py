@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsem.so")
 
 BC_DIRICHLET, BC_PERIODIC = 0, 1
-W_TOPHAT, W_ARITH = -1, -2
+W_TOPHAT, W_ARITH, W_MULT = -1, -2, -3
 NO_FIXED, NO_CEIL_P8, NO_FLOOR_P8, NO_CEIL_P2 = 0, 1, 2, 3
 FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
 
@@ -50,7 +50,11 @@ class _Overlap(C.Structure):
 
 class _Weights(C.Structure):
     _fields_ = [("wf", C.c_int32), ("alpha_x", C.POINTER(C.c_double)),
-                ("alpha_y", C.POINTER(C.c_double)), ("elem_params", C.POINTER(C.c_float))]
+                ("alpha_y", C.POINTER(C.c_double)), ("elem_params", C.POINTER(C.c_float)),
+                ("local_solve", C.c_int32)]
+
+
+LOCAL_MEAN, LOCAL_SEPARABLE = 0, 1
 
 
 _lib = None
@@ -128,7 +132,8 @@ class Solver:
 
     def __init__(self, xb, yb, p: int, bc: int = BC_DIRICHLET, overlap_rule: int = NO_FIXED,
                  n_o: int = 1, wf: int = 5, nu=None, precision: int = FP64, alpha_x=None,
-                 alpha_y=None, stream=None, overlaps=None, elem_params=None):
+                 alpha_y=None, stream=None, overlaps=None, elem_params=None,
+                 local_solve: int = LOCAL_MEAN):
         """elem_params: optional (n_e, 2) array of per-element (alpha_e, rho_e),
         e = ey * nx + ex (see sem_weights in include/sem.h)."""
         import torch
@@ -147,7 +152,8 @@ class Solver:
             elem_params, dtype=np.float32).reshape(-1)
         wts = _Weights(wf, None if self._ax is None else self._ax.ctypes.data_as(dp),
                        None if self._ay is None else self._ay.ctypes.data_as(dp),
-                       None if self._ep is None else self._ep.ctypes.data_as(C.POINTER(C.c_float)))
+                       None if self._ep is None else self._ep.ctypes.data_as(C.POINTER(C.c_float)),
+                       int(local_solve))
         nu_host = None
         if nu is not None:
             nu_host = np.ascontiguousarray(nu, dtype=np.float64)

@@ -163,6 +163,16 @@ class GaussianFieldNu:
         return x * self.omega[:, 0] + y * self.omega[:, 1] + self.phase
 
     def g(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        if x.ndim == 2 and y.ndim == 2 and x.shape[0] == 1 and y.shape[1] == 1:
+            # tensor grid (row of x, column of y): cos(a + b) = cos a cos b -
+            # sin a sin b per feature, summed over the features by two matrix
+            # products instead of one cosine per node and feature
+            a = x[0][:, None] * self.omega[:, 0] + self.phase     # (nx, K)
+            b = y[:, 0][:, None] * self.omega[:, 1]               # (ny, K)
+            s = np.cos(b) @ np.cos(a).T - np.sin(b) @ np.sin(a).T
+            return self.sigma * math.sqrt(2.0 / self.K) * s
         return self.sigma * math.sqrt(2.0 / self.K) * np.cos(self._arg(x, y)).sum(-1)
 
     def nu(self, x, y):

@@ -10,7 +10,7 @@ from paper_1512_02390_amd import workloads as W
 
 D, P = W.BC_DIRICHLET, W.BC_PERIODIC
 FIXED, CEIL8, FLOOR8, CEIL2 = 0, 1, 2, 3
-TOPHAT, ARITH = -1, -2
+TOPHAT, ARITH, MULT = -1, -2, -3
 
 
 @dataclass(frozen=True)
@@ -28,6 +28,8 @@ class Case:
     overlaps: tuple | None = None   # explicit n_o per level (entry 0 unused)
     alpha_seed: int | None = None   # random width scales per grid line in [0.2, 1]
     elem_seed: int | None = None    # random per-element (alpha_e, rho_e)
+    separable: bool = False         # separable local coefficients (variable nu)
+    strong_nu: bool = False         # nu field with length 0.2 and sigma 1
 
     def breaks(self):
         if self.stretched:
@@ -91,11 +93,27 @@ CASES = [
     Case("dir_p12_elem_varnu_stretch", 3, 4, 12, D, stretched=True, varnu=True, elem_seed=23),
     Case("dir_p16_elem_arith", 3, 3, 16, D, wf=ARITH, elem_seed=24),
     Case("dir_p32_elem", 2, 2, 32, D, elem_seed=25),
+    # separable local coefficients per subdomain (variable nu)
+    Case("dir_p8_sep_stretch", 5, 4, 8, D, stretched=True, rule=CEIL8, varnu=True,
+         separable=True),
+    Case("per_p6_sep_no2_strong", 4, 4, 6, P, n_o=2, varnu=True, separable=True, strong_nu=True),
+    Case("dir_p16_sep_strong", 3, 3, 16, D, rule=CEIL8, varnu=True, separable=True,
+         strong_nu=True),
+    Case("dir_p12_sep_no0", 4, 3, 12, D, n_o=0, varnu=True, separable=True),
+    # multiplicative Schwarz (Algorithm 1): sequential sweeps, Poisson
+    Case("dir_p4_mult", 5, 4, 4, D, n_o=1, wf=MULT),
+    Case("per_p6_mult_no2", 4, 3, 6, P, n_o=2, wf=MULT),
+    Case("dir_p8_mult_ceil8_stretch", 4, 3, 8, D, stretched=True, rule=CEIL8, wf=MULT),
+    Case("dir_p16_mult_no0", 3, 2, 16, D, n_o=0, wf=MULT),
 ]
 
 
 def nu_field(case: Case):
-    return W.GaussianFieldNu(seed=W.SEED_GRF, ell=0.5, sigma=0.3) if case.varnu else None
+    if not case.varnu:
+        return None
+    if case.strong_nu:
+        return W.GaussianFieldNu(seed=W.SEED_GRF, ell=0.2, sigma=1.0)
+    return W.GaussianFieldNu(seed=W.SEED_GRF, ell=0.5, sigma=0.3)
 
 
 def build_oracle(case: Case):
@@ -112,16 +130,19 @@ def build_oracle(case: Case):
     if ep is not None:
         ep = (ep[:, 0].reshape(case.ny, case.nx), ep[:, 1].reshape(case.ny, case.nx))
     return Multigrid(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, NU=NU,
-                     alpha_x=ax, alpha_y=ay, overlaps=case.overlaps, elem_params=ep), NU
+                     alpha_x=ax, alpha_y=ay, overlaps=case.overlaps, elem_params=ep,
+                     local_solve="separable" if case.separable else "mean"), NU
 
 
 def build_gpu(case: Case, NU=None, precision=0):
     from paper_1512_02390_amd.sem import Solver
     xb, yb = case.breaks()
     ax, ay = case.alphas()
+    from paper_1512_02390_amd.sem import LOCAL_MEAN, LOCAL_SEPARABLE
     return Solver(xb, yb, case.p, case.bc, case.rule, case.n_o, case.wf, nu=NU,
                   precision=precision, overlaps=case.overlaps, alpha_x=ax, alpha_y=ay,
-                  elem_params=case.elem_params())
+                  elem_params=case.elem_params(),
+                  local_solve=LOCAL_SEPARABLE if case.separable else LOCAL_MEAN)
 
 
 def rel_err(a, b) -> float:

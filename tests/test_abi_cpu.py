@@ -106,7 +106,7 @@ def test_setup_validation_without_device():
     lib.sem_setup.restype = C.c_int32
 
     def setup(nx=3, ny=3, p=4, bc=0, rule=1, n_o=1, wf=5, xb=None, yb=None, alpha=None,
-              elem=None):
+              elem=None, local=0):
         xb = np.linspace(0.0, 1.0, nx + 1) if xb is None else np.asarray(xb, dtype=np.float64)
         yb = np.linspace(0.0, 1.0, ny + 1) if yb is None else np.asarray(yb, dtype=np.float64)
         dp = C.POINTER(C.c_double)
@@ -115,7 +115,7 @@ def test_setup_validation_without_device():
         ax = None if alpha is None else np.asarray(alpha, dtype=np.float64)
         ep = None if elem is None else np.asarray(elem, dtype=np.float32).reshape(-1)
         w = S._Weights(wf, None if ax is None else ax.ctypes.data_as(dp), None,
-                       None if ep is None else ep.ctypes.data_as(C.POINTER(C.c_float)))
+                       None if ep is None else ep.ctypes.data_as(C.POINTER(C.c_float)), local)
         h = C.c_void_p(1)
         st = lib.sem_setup(C.byref(mesh), p, C.byref(ov), C.byref(w), None, 0, None, C.byref(h))
         assert h.value is None
@@ -138,5 +138,9 @@ def test_setup_validation_without_device():
     for e in (bad_alpha, big_alpha, bad_rho, nan_rho):
         assert setup(elem=e) == EINVAL
     assert setup(elem=good, alpha=[1.0, 1.0, 1.0, 1.0]) == EINVAL   # one or the other
+    assert setup(local=2) == EINVAL                      # unknown local solve
+    assert setup(wf=-3, alpha=[1.0, 1.0, 1.0, 1.0]) == -7   # multiplicative: paper weights only
+    assert setup(wf=-4) == EINVAL                        # no such weight function
+    assert setup(local=1) == EINVAL                      # separable needs a variable nu
     assert setup(xb=[0.0, 0.5, 0.5, 1.0]) == EDOM
     assert setup(yb=[0.0, 0.7, 0.4, 1.0]) == EDOM

@@ -32,6 +32,7 @@ NAME = {MIXED: "fp32", BF16: "bf16", FP16: "fp16"}
 SUBSET = [c for c in CASES if c.name in ("dir_p4_no1", "dir_p8_no3_stretch", "per_p6_no2_cubic",
                                          "dir_p16_ceil8", "dir_p12_ceil8_varnu_stretch",
                                          "dir_p32_ceil8", "dir_p32_levels_varnu_stretch",
+                                         "dir_p16_sep_strong",
                                          "dir_p12_elem_varnu_stretch", "dir_p32_elem")]
 
 

@@ -41,3 +41,17 @@ def test_workload_meshes():
     assert W.node_array_shape(64, 64, 8, W.BC_DIRICHLET) == (513, 513)      # 511^2 unknowns
     assert W.node_array_shape(128, 128, 16, W.BC_DIRICHLET) == (2049, 2049)
     assert W.node_array_shape(4, 4, 6, W.BC_PERIODIC) == (24, 24)
+
+
+def test_random_field_grid_evaluation_matches_pointwise():
+    """The tensor-grid fast path of GaussianFieldNu equals the per-node
+    evaluation of the same random Fourier features (rounding only)."""
+    import numpy as np
+    from paper_1512_02390_amd import workloads as W
+    f = W.GaussianFieldNu(ell=0.1)
+    x = np.linspace(0.0, 1.0, 37)
+    y = np.linspace(-0.3, 1.2, 29)
+    grid = W.nodal(f.nu, x, y)
+    X, Y = np.meshgrid(x, y)
+    point = np.array([f.nu(a, b) for a, b in zip(X.ravel(), Y.ravel())]).reshape(X.shape)
+    assert np.abs(grid - point).max() <= 1e-13 * np.abs(point).max()
