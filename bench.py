@@ -41,6 +41,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -346,6 +348,48 @@ def compare_run(name: str, precision: str, net, steps: int, warmup: int, imax: i
     return entry
 
 
+def compare_3d(n: int, p: int, n_o: int, steps: int, warmup: int, imax: int):
+    """3-D Poisson on the unit cube with n^3 elements of order p (the 3-D
+    extension, sem3_*): time to 1e-10 of MGCG(1,0), iterations, the true
+    residual and DOF/s per V-cycle."""
+    import torch
+    from paper_1512_02390_amd import workloads as W
+    from paper_1512_02390_amd.sem import Solver3
+    progress(f"comparison 3-D {n}^3 elements p={p} n_o={n_o}")
+    b = W.uniform_breaks(n, 1.0)
+    t0 = time.perf_counter()
+    s = Solver3(b, b, b, p, 0, n_o, 5)
+    setup_s = time.perf_counter() - t0
+    shape = s.level_info(s.L)[2]
+    g = W.rng(W.SEED_RHS)
+    f = g.uniform(-1.0, 1.0, size=shape)
+    f[[0, -1], :, :] = 0.0
+    f[:, [0, -1], :] = 0.0
+    f[:, :, [0, -1]] = 0.0
+    fb = torch.tensor(f, dtype=torch.float64, device="cuda")
+    u0 = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    for _ in range(max(warmup, 1)):
+        s.pcg_solve(u0.clone(), fb, imax, 1e-10)
+    us = [u0.clone() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cycles = 0
+    for k in range(steps):
+        it, hist, ok = s.pcg_solve(us[k], fb, imax, 1e-10)
+        cycles += it
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / steps
+    r = s.zeros()
+    s.residual(s.L, us[-1], fb, r)
+    true_ratio = float(torch.linalg.norm(r)) / float(hist[0])
+    dof = int(np.prod([x - 2 for x in shape]))
+    s.close()
+    return {"workload": f"3-D Poisson [0,1]^3, {n}^3 elements, p={p}, Dirichlet, n_o={n_o}",
+            "precision": "fp64", "solver": "MGCG mg10, w_5", "dof": dof, "setup_s": setup_s,
+            "time_to_1e-10_ms": 1e3 * dt if ok else None, "iterations": it, "converged": bool(ok),
+            "true_residual_ratio": true_ratio, "dof_per_s_per_vcycle": dof * cycles / (dt * steps)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -515,6 +559,7 @@ def main():
         cmp["c2_fp64_multiplicative"] = compare_run("c2", "fp64", None, 2, 1, args.imax,
                                                     cmp["c2_fp64_paper"]["time_to_1e-10_ms"],
                                                     wf=-3)
+        cmp["d3_fp64_paper"] = compare_3d(16, 8, 1, 10, 2, args.imax)
         out["comparisons"] = cmp
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")

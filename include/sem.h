@@ -311,6 +311,53 @@ sem_status sem_norm_noalloc(sem_handle h, const double *x, double *out);
 const char *sem_strerror(sem_status s);
 const char *sem_last_error(sem_handle h);
 
+/* ---- 3-D Poisson extension ----------------------------------------------
+ * The method in three dimensions, which the paper's conclusions (Section 5)
+ * name as the next step: -lap u = f on a tensor-product mesh of hexahedral
+ * spectral elements with homogeneous Dirichlet boundaries.  Everything
+ * carries over direction by direction:
+ *   A = M_z (x) M_y (x) L_x + M_z (x) L_y (x) M_x + L_z (x) M_y (x) M_x;
+ * extended-element subdomains are products of the 1-D windows (Section
+ * 3.1) with weights w_z w_y w_x; the local solves are 3-D fast
+ * diagonalisations; transfers interpolate along each axis (Section 3.2);
+ * the coarse problem (p = 1) is solved by a global fast diagonalisation;
+ * Algorithms 3 and 4 are unchanged.  FP64.  Node arrays are device arrays
+ * u[z][y][x] with (n_d p_l + 1) nodes per direction, boundary included and
+ * written as zero.  Subdomain width p_l + 1 + 2 n_o <= 15 (SEM_EUNSUP
+ * otherwise). */
+typedef struct sem3_ctx *sem3_handle;
+typedef struct {
+  int32_t nx, ny, nz;               /* elements per direction            */
+  const double *xb, *yb, *zb;       /* host arrays of n+1 increasing breaks */
+} sem_mesh3;
+/* wf: odd kappa or SEM_W_TOPHAT.  stream: hipStream_t (NULL = default). */
+sem_status sem3_setup(const sem_mesh3 *mesh, int32_t p, const sem_overlap *overlap, int32_t wf,
+                      void *stream, sem3_handle *out);
+sem_status sem3_destroy(sem3_handle h);
+sem_status sem3_num_levels(sem3_handle h, int32_t *n);
+/* nodes[3]: nodes along x, y, z of level `level`. */
+sem_status sem3_level_info(sem3_handle h, int32_t level, int32_t *p, int32_t *n_o, int64_t *nodes);
+/* r = f - A u (f = NULL: r = A u) on one level. */
+sem_status sem3_residual(sem3_handle h, int32_t level, const double *u, const double *f, double *r);
+/* n_it sweeps of Algorithm 2 on level >= 1, in place on u. */
+sem_status sem3_schwarz_smooth(sem3_handle h, int32_t level, double *u, const double *f,
+                               int32_t n_it);
+/* fc = I^T rf from level to level-1; uf += I uc from level-1 to level. */
+sem_status sem3_restrict(sem3_handle h, int32_t level, const double *rf, double *fc);
+sem_status sem3_prolong_add(sem3_handle h, int32_t level, const double *uc, double *uf);
+/* u0 = A_0^{-1} f0 on level 0. */
+sem_status sem3_coarse_solve(sem3_handle h, const double *f0, double *u0);
+/* One V-cycle (Algorithm 3) on the finest level; ns1/ns2 per level or NULL
+ * (MG(1,0)). */
+sem_status sem3_vcycle(sem3_handle h, double *u, const double *f, const int32_t *ns1,
+                       const int32_t *ns2);
+/* MGCG (Algorithm 4) to ||r|| <= rtol ||r_0||: *iters, hist[0..*iters]
+ * (host, imax+1 entries, may be NULL); SEM_ENOCONV at imax, SEM_ENAN on a
+ * non-finite residual; synchronises. */
+sem_status sem3_pcg_solve(sem3_handle h, double *u, const double *f, int32_t imax, double rtol,
+                          const int32_t *ns1, const int32_t *ns2, int32_t *iters, double *hist);
+const char *sem3_last_error(sem3_handle h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,56 @@
+// Launch interface of the 3-D kernels (three_d.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sem {
+
+constexpr int kMaxTile3 = 15;   // largest 3-D subdomain width (two m^3 FP64 tiles in LDS)
+
+// r = f - A u on one level (f null: r = A u); node array NZ x NY x NX.
+struct Res3Args {
+  int32_t nx, ny, nz, p;          // elements per direction, order
+  int32_t NX, NY, NZ;             // nodes per direction (n p + 1)
+  const double *u, *f;
+  double *r;
+  const double *Lhat, *w;         // (p+1)^2 reference stiffness, GLL weights
+  const double *sx, *sy, *sz;     // per element 2/h
+  const double *mx, *my, *mz;     // per element h/2
+};
+
+// One Schwarz correction: every subdomain of the level, added into u.
+struct Fdm3Args {
+  int32_t nx, ny, nz, p, n_o, m;
+  int32_t NX, NY, NZ;
+  const double *r;
+  double *u;
+  const double *Sx, *SxT, *lx;    // per x type: S, S^T (m x m), eigenvalues (m)
+  const double *Sy, *SyT, *ly;
+  const double *Sz, *SzT, *lz;
+  const int32_t *tx_of, *ty_of, *tz_of;   // type per element column / row / layer
+  const double *wx, *wy, *wz;     // per element m weights
+};
+
+// Band-matrix product along one axis (see k3_axis).
+struct Axis3Args {
+  int32_t d0, d1, d2;             // output dims (z, y, x)
+  int32_t axis;                   // 0 z, 1 y, 2 x
+  int32_t nin;                    // input length along the axis
+  const double *in;
+  double *out;
+  const int32_t *start, *cnt;     // per output index along the axis
+  const double *val;              // per output index, B values
+  int32_t B;
+  int32_t accumulate, zero_bnd;
+};
+
+void launch3_residual(const Res3Args &a, hipStream_t s);
+void launch3_fdm(const Fdm3Args &a, hipStream_t s);
+void launch3_axis(const Axis3Args &a, hipStream_t s);
+void launch3_eig_divide(double *x, int n0, int n1, int n2, const double *lz, const double *ly,
+                        const double *lx, hipStream_t s);
+void launch3_axpy(double *y, const double *x, double a, long n, hipStream_t s);
+void launch3_xpby(double *p, const double *z, double beta, long n, hipStream_t s);
+
+}  // namespace sem

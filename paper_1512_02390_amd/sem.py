@@ -30,7 +30,10 @@ EXPORTS = ["sem_setup", "sem_destroy", "sem_num_levels", "sem_level_info", "sem_
            "sem_elem_features",
            "sem_mlp_num_params", "sem_mlp_create", "sem_mlp_destroy", "sem_mlp_forward",
            "sem_mlp_gradient", "sem_mlp_train_step", "sem_mlp_get_params",
-           "sem_learned_params", "sem_norm_noalloc"]
+           "sem_learned_params", "sem_norm_noalloc",
+           "sem3_setup", "sem3_destroy", "sem3_num_levels", "sem3_level_info", "sem3_residual",
+           "sem3_schwarz_smooth", "sem3_restrict", "sem3_prolong_add", "sem3_coarse_solve",
+           "sem3_vcycle", "sem3_pcg_solve", "sem3_last_error"]
 
 
 class SemError(RuntimeError):
@@ -46,6 +49,12 @@ class _Mesh(C.Structure):
 
 class _Overlap(C.Structure):
     _fields_ = [("rule", C.c_int32), ("n_o", C.c_int32), ("per_level", C.POINTER(C.c_int32))]
+
+
+class _Mesh3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("xb", C.POINTER(C.c_double)), ("yb", C.POINTER(C.c_double)),
+                ("zb", C.POINTER(C.c_double))]
 
 
 class _Weights(C.Structure):
@@ -87,6 +96,19 @@ def load_library(path: str = LIB_PATH):
                                   C.POINTER(I32), C.POINTER(D)]
     lib.sem_norm.argtypes = [P, P, C.POINTER(D)]
     lib.sem_norm_noalloc.argtypes = [P, P, C.POINTER(D)]
+    lib.sem3_setup.argtypes = [C.POINTER(_Mesh3), I32, C.POINTER(_Overlap), I32, P, C.POINTER(P)]
+    lib.sem3_destroy.argtypes = [P]
+    lib.sem3_num_levels.argtypes = [P, C.POINTER(I32)]
+    lib.sem3_level_info.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]
+    lib.sem3_residual.argtypes = [P, I32, P, P, P]
+    lib.sem3_schwarz_smooth.argtypes = [P, I32, P, P, I32]
+    lib.sem3_restrict.argtypes = [P, I32, P, P]
+    lib.sem3_prolong_add.argtypes = [P, I32, P, P]
+    lib.sem3_coarse_solve.argtypes = [P, P, P]
+    lib.sem3_vcycle.argtypes = [P, P, P, P, P]
+    lib.sem3_pcg_solve.argtypes = [P, P, P, I32, D, P, P, C.POINTER(I32), C.POINTER(D)]
+    lib.sem3_last_error.argtypes = [P]
+    lib.sem3_last_error.restype = C.c_char_p
     lib.sem_timing_enable.argtypes = [P, I32, I32]
     lib.sem_timing_read.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
     lib.sem_timing_read_all.argtypes = [P, C.POINTER(I64), C.POINTER(D)]
@@ -371,3 +393,86 @@ def learned_params(pred, nx: int, ny: int, p: int, bc: int):
                                   ax.ctypes.data_as(dp), ay.ctypes.data_as(dp)),
            "sem_learned_params")
     return list(ov), ax, ay
+
+
+class Solver3:
+    """Handle of one 3-D Poisson problem (all multigrid levels) on the current
+    device: the sem3_* entry points, argument marshalling only."""
+
+    def __init__(self, xb, yb, zb, p: int, overlap_rule: int = NO_FIXED, n_o: int = 1,
+                 wf: int = 5, stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self._b = [np.ascontiguousarray(b, dtype=np.float64) for b in (xb, yb, zb)]
+        dp = C.POINTER(C.c_double)
+        mesh = _Mesh3(len(self._b[0]) - 1, len(self._b[1]) - 1, len(self._b[2]) - 1,
+                      *[b.ctypes.data_as(dp) for b in self._b])
+        ov = _Overlap(overlap_rule, n_o, None)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.sem3_setup(C.byref(mesh), p, C.byref(ov), wf, C.c_void_p(stream), C.byref(h))
+        if st != 0:
+            raise SemError(st, "sem3_setup failed")
+        self.h = h
+        n = C.c_int32()
+        self._check(self.lib.sem3_num_levels(self.h, C.byref(n)))
+        self.L = n.value - 1
+
+    def _check(self, st):
+        if st != 0:
+            raise SemError(st, self.lib.sem3_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sem3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level: int):
+        """(p_l, n_o, (nodes z, y, x))."""
+        p, no = C.c_int32(), C.c_int32()
+        nodes = (C.c_int64 * 3)()
+        self._check(self.lib.sem3_level_info(self.h, level, C.byref(p), C.byref(no), nodes))
+        return p.value, no.value, (nodes[2], nodes[1], nodes[0])
+
+    def zeros(self, level: int | None = None):
+        shape = self.level_info(self.L if level is None else level)[2]
+        return self.torch.zeros(shape, dtype=self.torch.float64, device="cuda")
+
+    def residual(self, level: int, u, f, r):
+        self._check(self.lib.sem3_residual(self.h, level, _ptr(u), _ptr(f), _ptr(r)))
+
+    def schwarz_smooth(self, level: int, u, f, n_it: int = 1):
+        self._check(self.lib.sem3_schwarz_smooth(self.h, level, _ptr(u), _ptr(f), n_it))
+
+    def restrict(self, level: int, rf, fc):
+        self._check(self.lib.sem3_restrict(self.h, level, _ptr(rf), _ptr(fc)))
+
+    def prolong_add(self, level: int, uc, uf):
+        self._check(self.lib.sem3_prolong_add(self.h, level, _ptr(uc), _ptr(uf)))
+
+    def coarse_solve(self, f0, u0):
+        self._check(self.lib.sem3_coarse_solve(self.h, _ptr(f0), _ptr(u0)))
+
+    def vcycle(self, u, f, ns1=None, ns2=None):
+        self._check(self.lib.sem3_vcycle(self.h, _ptr(u), _ptr(f), _i32_array(ns1), _i32_array(ns2)))
+
+    def pcg_solve(self, u, f, imax: int = 100, rtol: float = 1e-10, ns1=None, ns2=None):
+        """Returns (iterations, residual history, converged)."""
+        it = C.c_int32()
+        hist = np.zeros(imax + 1)
+        st = self.lib.sem3_pcg_solve(self.h, _ptr(u), _ptr(f), imax, rtol, _i32_array(ns1),
+                                     _i32_array(ns2), C.byref(it),
+                                     hist.ctypes.data_as(C.POINTER(C.c_double)))
+        if st not in (0, -5):
+            self._check(st)
+        return it.value, hist[: it.value + 1], st == 0

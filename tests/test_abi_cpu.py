@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_1512_02390_amd", "libsem.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sem_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sem3?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_header_is_c():
