@@ -413,6 +413,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed / learned vs plain FP64 comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="only run the 3-D comparison (16^3 elements, p=8) and print its entry")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -432,6 +434,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
+    if args.only_3d:
+        print(json.dumps(compare_3d(16, 8, 1, args.steps, args.warmup, args.imax)), flush=True)
         return
 
     from paper_1512_02390_amd import metrics as MT
