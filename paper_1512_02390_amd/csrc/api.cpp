@@ -1006,7 +1006,10 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
     h->pq = dalloc<double>(h->pool, n);
     h->pz = dalloc<double>(h->pool, n);
     h->pro = dalloc<double>(h->pool, n);
-    h->partial = dalloc<double>(h->pool, std::max<long>(2 * kRedBlocks, residual_waves(h->lev[L].g)));
+    const Grid &gt = h->lev[L].g;
+    const long nblk = std::max({residual_blocks(gt, false, 8), residual_blocks(gt, true, 8),
+                                residual_blocks(gt, false, 4), residual_blocks(gt, true, 4)});
+    h->partial = dalloc<double>(h->pool, std::max<long>(2 * kRedBlocks, nblk));
     h->scal = dalloc<double>(h->pool, 16);
     h->part_rr = dalloc<double>(h->pool, kRedBlocks);
     h->part_d2 = dalloc<double>(h->pool, 2 * kRedBlocks);
@@ -1049,6 +1052,8 @@ void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x 
               double *dot_res = nullptr) {
   Level &L = h->lev[l];
   Tables<T> &t = tabs<T>(L);
+  // the kernels load f and dot_x through one set of registers
+  if (f && dot_x) throw Fail{SEM_EINVAL, "residual: right-hand side and dot operand both given"};
   ResidualArgs<T> a{L.g, u, f, out, t.Lhat, t.D, t.DT, t.w, t.sx, t.sy, t.mx, t.my, t.nu, t.nuT,
                     t.gy, t.gx, dot_x, dot_x ? h->partial : nullptr};
   {
@@ -1057,7 +1062,9 @@ void residual(sem_ctx *h, int l, const T *u, const T *f, T *out, const T *dot_x 
   }
   // dot_res = sum of dot_x * out, from the kernel's per-block partial sums
   // (without dot_res they stay in h->partial for the consumer to add)
-  if (dot_x && dot_res) launch_reduce(h->partial, (int)residual_waves(L.g), dot_res, h->stream);
+  if (dot_x && dot_res)
+    launch_reduce(h->partial, (int)residual_blocks(L.g, t.nu != nullptr, sizeof(T)), dot_res,
+                  h->stream);
 }
 
 template <typename T>
@@ -1470,7 +1477,7 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     // No reduction has a launch of its own: the kernels that consume a dot
     // product add its partial sums themselves (fixed order), and the host
     // adds the r.r partials it copies for the stopping test.
-    const int npq = (int)residual_waves(top.g);
+    const int npq = (int)residual_blocks(top.g, top.td.nu != nullptr, sizeof(double));
     auto q_and_pq = [&] {
       residual<double>(h, L, p, nullptr, q, p);   // q = A p; p.q partials in h->partial
     };

@@ -43,17 +43,29 @@ struct ResidualArgs {
   // flux scratch of the variable-nu residual (owned by the level):
   // gy: (ny (p+1)) x cols, gx: (nx (p+1)) x rows
   T *gy, *gx;
-  // optional fused dot product: when dot_x is non-null, wavefront b of the
-  // residual kernel writes sum over its owned nodes of dot_x * out to
-  // dot_part[b] (residual_waves() entries, summed by launch_reduce)
+  // optional fused dot product (with f null only): when dot_x is non-null,
+  // block b of the residual kernel writes sum over its owned nodes of
+  // dot_x * out to dot_part[b] (residual_blocks() entries, summed by
+  // launch_reduce)
   const T *dot_x;
   double *dot_part;
 };
-// Number of wavefronts (one per element strip and element row) of the
-// residual kernels on a grid.
-inline long residual_waves(const Grid &g) {
-  const int ne = 64 / g.p;
-  return (long)((g.nx + ne - 1) / ne) * g.ny;
+// Element rows per block of the residual kernels: for the Poisson operator as
+// many as fit about 44 KB of LDS, at most 4 (the kernel's template argument
+// and the block count below both come from here); elem_bytes: sizeof of the
+// arithmetic type.
+constexpr int residual_rows(int p, bool nu, int elem_bytes) {
+  if (nu) return 1;   // the variable-nu pair keeps one element row per block
+  const int W = (64 / p) * p, LW = W + p + 1;
+  const long per_row = (long)(p + 1) * LW * elem_bytes + (p > 16 ? (long)p * W * elem_bytes : 0);
+  const long k = 45056 / per_row;
+  return k >= 4 ? 4 : (k < 1 ? 1 : (int)k);
+}
+// Number of blocks (strips of 64/p elements times residual_rows element rows)
+// of the residual kernel on a grid.
+inline long residual_blocks(const Grid &g, bool nu, int elem_bytes) {
+  const int ne = 64 / g.p, kr = residual_rows(g.p, nu, elem_bytes);
+  return (long)((g.nx + ne - 1) / ne) * ((g.ny + kr - 1) / kr);
 }
 
 // Matrix-core operands of the reduced-precision Schwarz kernel, prepared at

@@ -67,6 +67,23 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
+// Per-block partial of the fused dot product: the wavefronts' sums added in
+// wavefront order, written by thread 0 to part[block].  Every thread of the
+// block calls it (it holds a barrier when the block has several wavefronts).
+__device__ __forceinline__ void block_dot_part(double dsum, double *dsw, int wi, int nwaves,
+                                               double *part) {
+  dsum = wave_sum64(dsum);
+  if (nwaves > 1) {
+    if ((threadIdx.x & 63) == 0) dsw[wi] = dsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      dsum = dsw[0];
+      for (int i = 1; i < nwaves; ++i) dsum += dsw[i];
+    }
+  }
+  if (threadIdx.x == 0) part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
+}
+
 // Load a node-array segment of P+1 consecutive nodes along a row or a column.
 template <typename T, int P>
 __device__ __forceinline__ void load_col(const T *__restrict__ u, int row0, int col, const Grid &g,
@@ -112,8 +129,8 @@ __device__ __forceinline__ void share(int n, int w, int &lo, int &hi) {
   hi = min(n, lo + h);
 }
 
-template <typename T, int P, int NW>
-__global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
+template <typename T, int P, int NW, int KR>
+__global__ __launch_bounds__(64 * NW * KR) void k_residual(ResidualArgs<T> A) {
   constexpr int NE = 64 / P;
   constexpr int W = NE * P;
   constexpr int LW = W + P + 1;
@@ -121,25 +138,31 @@ __global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
   // larger orders keep them apart so that the left segment can be read after
   // the main contraction without holding it in registers.
   constexpr bool kAlias = P <= 16;
-  __shared__ T su[P][LW];                         // owned rows, halo p left, 1 right
-  __shared__ T sxp_own[kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
-  __shared__ double dsum1;  // wave 1's part of the fused dot product
+  // rows 0..P of the element row; rows below P with a halo of p columns on the
+  // left and one on the right, row P (the top row) on the strip's columns only
+  __shared__ T su_all[KR][P + 1][LW];
+  __shared__ T sxp_all[KR][kAlias ? 1 : P][kAlias ? 1 : W];  // x-part per owned node
+  __shared__ T ytop[KR][W];        // y-part of element row k at its top row (for row k + 1)
+  __shared__ double dsw[KR * NW];  // per-wave parts of the fused dot product
   const Grid g = A.g;
   const int per = g.periodic;
   const int lane = threadIdx.x & 63;
-  // wave w computes the output rows / x-part columns [lo, hi)
-  const int w = NW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  // wave (k, w): element row k of the block, output rows / x-part columns [lo, hi)
+  const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k = wi / NW, w = wi - (wi / NW) * NW;
   int lo, hi;
   share<NW>(P, w, lo, hi);
   const int e0 = blockIdx.x * NE;
-  const int ey = blockIdx.y;
+  const int ey = blockIdx.y * KR + k;
+  const bool act = ey < g.ny;   // element rows past the last: barriers only
   const int c0 = e0 * P;
   const int r0 = ey * P;
   const int eym = per ? wrap(ey - 1, g.ny) : ey - 1;
   const bool has_below = per || ey > 0;
+  T(&su)[P + 1][LW] = su_all[k];
   auto sxp = [&](int a, int c) -> T & {
     if constexpr (kAlias) return su[a][c];
-    else return sxp_own[a][c];
+    else return sxp_all[k][a][c];
   };
 
   // ---- column of the element row (lane = column) ---------------------------
@@ -147,89 +170,94 @@ __global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
   const int gc = c0 + c;
   // last column needed by this strip: the right end of its last element
   const int last_col = min(c0 + W, g.nx * P);
-  const bool col_lane = c < W && gc <= last_col;
-  T yv[P + 1];     // the column's u segment
-  load_col<T, P>(A.u, r0, gc, g, col_lane, yv);
-  if (col_lane && w == 0) {
+  const bool col_lane = act && c < W && gc <= last_col;
+  const int q = c / P, al = c - (c / P) * P;
+  const int ex = e0 + q;
+  const bool out_lane = col_lane && ex < g.nx;
+  // right-hand side and dot-product operand of this wave's output rows, issued
+  // first so that their latency overlaps the staging and the x-part
+  // (f and dot_x are never both given: one array of loads serves either)
+  constexpr int HR = (P + NW - 1) / NW;
+  const T *hsrc = A.f ? A.f : A.dot_x;
+  T hv[HR];
 #pragma unroll
-    for (int a = 0; a < P; ++a) su[a][P + c] = yv[a];
+  for (int t = 0; t < HR; ++t) {
+    const long idx = (long)(r0 + lo + t) * g.cols + gc;
+    const bool on = out_lane && lo + t < hi;
+    hv[t] = (on && hsrc) ? hsrc[idx] : T(0);
+  }
+  // the column's u segment: wave 0 loads it and stages it for the others
+  T yv[P + 1];
+  if (w == 0 && act) {
+    load_col<T, P>(A.u, r0, gc, g, col_lane, yv);
+    if (col_lane) {
+#pragma unroll
+      for (int a = 0; a <= P; ++a) su[a][P + c] = yv[a];
+    }
   }
   // halo columns of the owned rows
-  if (w == 0 && (lane < P || (lane == P && c0 + W <= last_col))) {
-    const int k = lane < P ? lane : P + W;
+  if (act && w == 0 && (lane < P || (lane == P && c0 + W <= last_col))) {
+    const int kk = lane < P ? lane : P + W;
     const int col = lane < P ? c0 - P + lane : c0 + W;
 #pragma unroll
-    for (int a = 0; a < P; ++a) su[a][k] = node_value(A.u, r0 + a, col, g.rows, g.cols, per);
+    for (int a = 0; a < P; ++a) su[a][kk] = node_value(A.u, r0 + a, col, g.rows, g.cols, per);
   }
-  // the element below contributes to the shared bottom row (local node P)
+  // the first element row of the block recomputes the contribution of the
+  // element below to its shared bottom row; the others take it from the
+  // element row below them in the block (ytop, after the x-part)
   T extra_y = T(0);
-  if (has_below && lo == 0) {
+  if (k == 0 && has_below && lo == 0 && act) {
     T seg[P + 1];
     load_col<T, P>(A.u, r0 - P, gc, g, col_lane, seg);
     extra_y = A.sy[eym] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), seg);
   }
   __syncthreads();
+  if (w > 0 && col_lane) {
+#pragma unroll
+    for (int a = 0; a <= P; ++a) yv[a] = su[a][P + c];
+  }
+  // the y-part of this element row at its top row, for the element row above
+  if (w == NW - 1 && k + 1 < KR && col_lane)
+    ytop[k][c] = A.sy[ey] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), yv);
 
   // ---- x-part (lane = (row a, element q)) -------------------------------------
   {
     const int q = lane / P, a = lane - (lane / P) * P;
     const int ex = e0 + q;
-    const bool xlane = lane < W && ex < g.nx;
+    const bool xlane = act && lane < W && ex < g.nx;
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
-    T seg[P + 1], segl[kAlias ? P + 1 : 1];
+    // contribution of the left neighbour to the shared left node, formed
+    // first so that only the own segment stays in registers
+    T extra_x = T(0);
+    T seg[P + 1];
+    if (xlane && has_left && lo == 0) {
+#pragma unroll
+      for (int b = 0; b <= P; ++b) seg[b] = su[a][q * P + b];
+      extra_x = A.sx[exm] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), seg);
+    }
     if (xlane) {
 #pragma unroll
       for (int b = 0; b <= P; ++b) seg[b] = su[a][P + q * P + b];
-      if constexpr (kAlias) {
-#pragma unroll
-        for (int b = 0; b <= P; ++b) segl[b] = su[a][q * P + b];
-      }
     }
     if constexpr (kAlias) __syncthreads();   // the results overwrite su below
     if (xlane) {
       T *xrow = &sxp(a, q * P);
       rows_apply<T, P>(as_const(A.Lhat) + lo * (P + 1), seg, A.sx[ex], xrow + lo, 1, hi - lo);
-      if (has_left && lo == 0) {
-        // contribution of the left neighbour to the shared left node
-        auto extra_of = [&](const T(&sl)[P + 1]) -> T {
-          return A.sx[exm] * udot<T, P + 1>(as_const(A.Lhat) + P * (P + 1), sl);
-        };
-        if constexpr (kAlias) {
-          xrow[0] += extra_of(segl);
-        } else {
-#pragma unroll
-          for (int b = 0; b <= P; ++b) seg[b] = su[a][q * P + b];
-          xrow[0] += extra_of(seg);
-        }
-      }
+      if (lo == 0) xrow[0] += extra_x;
     }
   }
   __syncthreads();
 
   // ---- y-part combined with the x-part and the assembled mass (lane = column) ----
   //   (A u)(row, col) = M_y(row) xpart + M_x(col) ypart
+  if (k > 0 && lo == 0 && col_lane) extra_y = ytop[k - 1][c];
   double dsum = 0.0;   // fused dot product (see ResidualArgs::dot_x)
-  const int q = c / P, al = c - (c / P) * P;
-  const int ex = e0 + q;
-  if (col_lane && ex < g.nx) {
+  if (out_lane) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const cptr<T> Op = as_const(A.Lhat);
     const T sy = A.sy[ey];
-    // the right-hand side and dot-product operand of this wave's rows, all
-    // loaded before the first store (out may alias neither, but the compiler
-    // cannot tell, and would otherwise wait one memory round trip per row)
-    constexpr int HR = (P + NW - 1) / NW;
-    T fv[HR], xv[HR];
-#pragma unroll
-    for (int t = 0; t < HR; ++t) {
-      const long idx = (long)(r0 + lo + t) * g.cols + gc;
-      const bool on = lo + t < hi;
-      fv[t] = (on && A.f) ? A.f[idx] : T(0);
-      xv[t] = (on && A.dot_x) ? A.dot_x[idx] : T(0);
-    }
 #pragma unroll
     for (int t = 0; t < HR; ++t) {
       const int a = lo + t;
@@ -242,29 +270,21 @@ __global__ __launch_bounds__(64 * NW) void k_residual(ResidualArgs<T> A) {
       const int row = r0 + a;
       const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
       const T au = myr * sxp(a, c) + mxc * yp;
-      T v = A.f ? fv[t] - au : au;
+      T v = A.f ? hv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
-      dsum += (double)v * (double)xv[t];
+      if (A.dot_x) dsum += (double)v * (double)hv[t];
     }
     if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
-  if (w == 0 && !per && lane == 0 && e0 + NE >= g.nx) {
+  if (act && w == 0 && !per && lane == 0 && e0 + NE >= g.nx) {
 #pragma unroll
     for (int a = 0; a < P; ++a) A.out[(long)(r0 + a) * g.cols + g.cols - 1] = T(0);
     if (ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + g.cols - 1] = T(0);
   }
-  if (A.dot_x) {
-    dsum = wave_sum64(dsum);
-    if constexpr (NW > 1) {
-      // wave 0 + wave 1, in that order
-      if (w == 1 && lane == 0) dsum1 = dsum;
-      __syncthreads();
-      if (w == 0) dsum += dsum1;
-    }
-    if (w == 0 && lane == 0) A.dot_part[(long)blockIdx.y * gridDim.x + blockIdx.x] = dsum;
-  }
+  if (A.dot_x) block_dot_part(dsum, dsw, wi, KR * NW, A.dot_part);
 }
+
 // ---------------------------------------------------------------------------
 // Variable-coefficient residual in two passes (Section 4, operator B(nu)):
 // B(nu) u = sum over elements of D_y^T G_y + D_x^T G_x with the fluxes
@@ -472,14 +492,16 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
 template <typename T, int P>
 void launch_residual_p(const ResidualArgs<T> &a, hipStream_t s) {
   constexpr int NE = 64 / P;
-  dim3 grid(ceil_div(a.g.nx, NE), a.g.ny);
   if (a.nu) {
     constexpr int NW = nu_waves<P>();
+    static_assert(residual_rows(P, true, sizeof(T)) == 1, "one element row per block");
+    dim3 grid(ceil_div(a.g.nx, NE), a.g.ny);
     klaunch((k_flux<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
     klaunch((k_residual_nu<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
   } else {
-    constexpr int NW = poisson_waves<P>();
-    klaunch((k_residual<T, P, NW>), grid, dim3(64 * NW), 0, s, a);
+    constexpr int NW = poisson_waves<P>(), KR = residual_rows(P, false, sizeof(T));
+    dim3 grid(ceil_div(a.g.nx, NE), ceil_div(a.g.ny, KR));
+    klaunch((k_residual<T, P, NW, KR>), grid, dim3(64 * NW * KR), 0, s, a);
   }
 }
 
