@@ -1183,6 +1183,12 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0, bool u0_clear = fa
   if (!u0_clear) launch_fill<double>(u0, c.n(), 0.0, s);
   if (h->cMinv) {
     launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
+  } else if (nx <= kSandwichMax && ny <= kSandwichMax) {
+    // T2 = (S_y^T F S_x) .* Dinv ; U = S_y T2 S_x^T, one launch each
+    launch_sandwich(ny, nx, h->cSy, 1, ny, f + h->coff, ld, h->cSx, nx, 1, h->cDinv, nx, h->cT2,
+                    nx, s);
+    launch_sandwich(ny, nx, h->cSy, ny, 1, h->cT2, nx, h->cSx, 1, nx, nullptr, 0, u0 + h->coff,
+                    ld, s);
   } else {
     // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T
     launch_gemm(ny, nx, ny, h->cSy, 1, ny, f + h->coff, ld, 1, h->cT1, nx, nullptr, 0, s);
@@ -1455,7 +1461,6 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
       launch_sub_mean(top.g, q, sc + 8, st);
       fp = q;
     }
-    launch_fill<double>(ro, n, 0.0, st);
     residual<double>(h, L, u, fp, r);
     launch_dot(r, r, n, h->partial, sc + 2, st);
     const double r0 = std::sqrt(read_scalar(h, sc + 2));
@@ -1487,8 +1492,8 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
       // the update below already wrote the cycle's inputs (prepared)
       precondition(h, r, z, ns1, ns2, true, ro, mixed ? h->part_d2 : nullptr);
       if (!mixed) launch_dot2_partials(z, r, ro, n, h->part_d2, st);   // z.(r - r_old), z.r
-      // beta = z.(r - r_old) / delta; p = z + beta p; r_old = r; next delta = z.r
-      launch_cg_direction2(h->part_d2, delta, delta_next, p, z, ro, r, n, st);
+      // beta = z.(r - r_old) / delta; p = z + beta p; next delta = z.r
+      launch_cg_direction2(h->part_d2, delta, delta_next, p, z, n, st);
       std::swap(delta, delta_next);
     };
     int it = 0;
@@ -1497,9 +1502,13 @@ sem_status sem_pcg_solve(sem_handle h, double *u, const double *f, int32_t imax,
     if (!done && imax > 0) q_and_pq();
     for (it = 1; it <= imax && !done; ++it) {
       // alpha = delta / p.q; also writes the next cycle's inputs
-      const int nrr = launch_cg_update2(delta, h->partial, npq, u, p, r, q, n, h->part_rr, st,
-                                        mixed ? top.ff : nullptr, mixed ? top.uf : nullptr,
+      // the new residual goes into the buffer of the one before the current
+      // one, and the current one becomes r_old (Algorithm 4's first r_old is zero)
+      const int nrr = launch_cg_update2(delta, h->partial, npq, u, p, r, ro, q, n, h->part_rr,
+                                        st, mixed ? top.ff : nullptr, mixed ? top.uf : nullptr,
                                         mixed ? nullptr : z);
+      std::swap(r, ro);
+      if (it == 1) launch_fill<double>(ro, n, 0.0, st);
       double *slot = h->pin + (size_t)(it & 1) * kRedBlocks;
       HIP_OK(hipMemcpyAsync(slot, h->part_rr, nrr * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_OK(hipEventRecord(h->nev[it & 1], st));

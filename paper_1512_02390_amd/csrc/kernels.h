@@ -148,6 +148,14 @@ void launch_prolong(const Grid &gf, const Grid &gc, const T *uc, T *uf, const T 
 void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const double *B,
                  long brs, long bcs, double *C, long ldc, const double *S, long lds,
                  hipStream_t s);
+// C (nr x nc) = S .* (L F R) in one launch, for nr, nc <= kSandwichMax: L is
+// nr x nr with element (i, k) at L[i lrs + k lcs], F nr x nc with leading
+// dimension ldf, R nc x nc with element (k, j) at R[k rrs + j rcs]; S (null:
+// no scaling) and C with leading dimensions lds and ldc.
+constexpr int kSandwichMax = 128;
+void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const double *F,
+                     long ldf, const double *R, long rrs, long rcs, const double *S, long lds,
+                     double *C, long ldc, hipStream_t s);
 // y = Minv x on the unknown block of a node array (dense inverse, var nu).
 void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
                          int nux, double *y, hipStream_t s);
@@ -183,19 +191,19 @@ void launch_dot2_partials(const double *z, const double *r, const double *ro, lo
 //   z = (double) z32, and the partials as above
 void launch_convert_dot2_partials(const float *z32, double *z, const double *r, const double *ro,
                                   long n, double *partial, hipStream_t s);
-//   alpha = delta[0] / sum(pq_part[0 .. npq)); u += alpha p; r -= alpha q;
-//   rr_part[b] = partial sums of r.r (returned: their count).  When non-null
-//   it also writes the next V-cycle's inputs: r32 = (float) r, z32 = 0 or
-//   z64 = 0
+//   alpha = delta[0] / sum(pq_part[0 .. npq)); u += alpha p;
+//   r_out = r_in - alpha q (r_in is left as it was: the caller keeps it as
+//   the previous residual); rr_part[b] = partial sums of r_out.r_out
+//   (returned: their count).  When non-null it also writes the next
+//   V-cycle's inputs: r32 = (float) r_out, z32 = 0 or z64 = 0
 int launch_cg_update2(const double *delta, const double *pq_part, int npq, double *u,
-                      const double *p, double *r, const double *q, long n, double *rr_part,
-                      hipStream_t s, float *r32 = nullptr, float *z32 = nullptr,
-                      double *z64 = nullptr);
-//   beta = sum(slot 0) / delta[0]; p = z + beta p; ro = r; delta_new[0] = sum(slot 1)
+                      const double *p, const double *r_in, double *r_out, const double *q,
+                      long n, double *rr_part, hipStream_t s, float *r32 = nullptr,
+                      float *z32 = nullptr, double *z64 = nullptr);
+//   beta = sum(slot 0) / delta[0]; p = z + beta p; delta_new[0] = sum(slot 1)
 //   (d2_part as written by launch_dot2_partials for the same n)
 void launch_cg_direction2(const double *d2_part, const double *delta, double *delta_new,
-                          double *p, const double *z, double *ro, const double *r, long n,
-                          hipStream_t s);
+                          double *p, const double *z, long n, hipStream_t s);
 // y += alpha x
 void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s);
 

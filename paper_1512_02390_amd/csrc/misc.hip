@@ -2,6 +2,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <stdexcept>
+
 namespace sem {
 
 LaunchTiming &launch_timing() {
@@ -34,6 +36,60 @@ __global__ void k_gemm(int M, int N, int K, const double *__restrict__ A, long a
   if (row < M && col < N) {
     if (S) acc *= S[row * lds_ + col];
     C[row * ldc + col] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-sided product C = S .* (L F R) for the coarse fast diagonalisation, one
+// launch instead of two GEMMs.  One block of 8 wavefronts per 16-column strip
+// of C: wavefront w forms rows [16 w, 16 w + 16) of G = F R(:, strip) with the
+// FP64 matrix-core product v_mfma_f64_16x16x4 (A 16x4: lane i + 16 k holds
+// A(i, k); B 4x16: lane j + 16 k holds B(k, j); the 16x16 result: lane
+// j + 16 g holds rows g, g + 4, g + 8, g + 12 of column j), keeps G in LDS, then forms
+// the same rows of L G.  All operand loads of both products are issued
+// before the first product.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kSwSteps = kSandwichMax / 4;   // k steps of 4
+
+__global__ __launch_bounds__(512) void k_sandwich(int nr, int nc, const double *__restrict__ L,
+                                                  long lrs, long lcs, const double *__restrict__ F,
+                                                  long ldf, const double *__restrict__ R, long rrs,
+                                                  long rcs, const double *__restrict__ S,
+                                                  long lds_, double *__restrict__ C, long ldc) {
+  __shared__ double G[kSandwichMax][17];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int row = w * 16 + i;          // A-operand row of this lane
+  const int col = blockIdx.x * 16 + i; // B-operand column of this lane (first product)
+  double a1[kSwSteps], b1[kSwSteps], a2[kSwSteps];
+#pragma unroll
+  for (int t = 0; t < kSwSteps; ++t) {
+    const int k = 4 * t + kq;
+    a1[t] = (row < nr && k < nc) ? F[(long)row * ldf + k] : 0.0;
+    b1[t] = (k < nc && col < nc) ? R[(long)k * rrs + (long)col * rcs] : 0.0;
+    a2[t] = (row < nr && k < nr) ? L[(long)row * lrs + (long)k * lcs] : 0.0;
+  }
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kSwSteps; ++t)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1[t], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) G[w * 16 + kq + 4 * r][i] = acc[r];
+  __syncthreads();
+  dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kSwSteps; ++t)
+    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[t], G[4 * t + kq][i], acc2, 0, 0, 0);
+  const int cj = blockIdx.x * 16 + i;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ci = w * 16 + kq + 4 * r;
+    if (ci < nr && cj < nc) {
+      double v = acc2[r];
+      if (S) v *= S[(long)ci * lds_ + cj];
+      C[(long)ci * ldc + cj] = v;
+    }
   }
 }
 
@@ -223,7 +279,8 @@ __global__ void k_axpy(double alpha, const double *__restrict__ x, double *__res
 // zero initial guess in FP32 or FP64).
 __global__ void k_cg_update2(const double *__restrict__ delta, const double *__restrict__ pq_part,
                              int npq, double *__restrict__ u, const double *__restrict__ p,
-                             double *__restrict__ r, const double *__restrict__ q, long n,
+                             const double *__restrict__ r_in, double *__restrict__ r_out,
+                             const double *__restrict__ q, long n,
                              double *__restrict__ rr_part, float *__restrict__ r32,
                              float *__restrict__ z32, double *__restrict__ z64) {
   __shared__ double red[RT];
@@ -231,8 +288,8 @@ __global__ void k_cg_update2(const double *__restrict__ delta, const double *__r
   double s = 0.0;
   for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
     u[i] = fma(alpha, p[i], u[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
+    const double ri = fma(-alpha, q[i], r_in[i]);
+    r_out[i] = ri;
     s = fma(ri, ri, s);
     if (r32) r32[i] = (float)ri;
     if (z32) z32[i] = 0.0f;
@@ -244,20 +301,19 @@ __global__ void k_cg_update2(const double *__restrict__ delta, const double *__r
 
 // Polak-Ribiere direction with the reductions folded in: num = z.(r - ro) and
 // delta_new = z.r are the sums of the nb partials in d2_part (slots 0 and 1,
-// kRedBlocks apart); beta = num / delta; p = z + beta p; ro = r; block 0
-// stores delta_new (a different slot than delta: other blocks still read it).
+// kRedBlocks apart); beta = num / delta; p = z + beta p; block 0 stores
+// delta_new (a different slot than delta: other blocks still read it).  The
+// previous residual needs no copy: the update writes the new one into the
+// other of two buffers.
 __global__ void k_cg_direction2(const double *__restrict__ d2_part, int nb,
                                 const double *__restrict__ delta, double *__restrict__ delta_new,
-                                double *__restrict__ p, const double *__restrict__ z,
-                                double *__restrict__ ro, const double *__restrict__ r, long n) {
+                                double *__restrict__ p, const double *__restrict__ z, long n) {
   __shared__ double red[RT];
   const double num = sum_partials(d2_part, nb, red);
   const double dn = sum_partials(d2_part + kRedBlocks, nb, red);
   const double beta = num / delta[0];
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT) {
+  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)gridDim.x * RT)
     p[i] = fma(beta, p[i], z[i]);
-    ro[i] = r[i];
-  }
   if (blockIdx.x == 0 && threadIdx.x == 0) delta_new[0] = dn;
 }
 
@@ -274,6 +330,16 @@ void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const
   dim3 grid(ceil_div(N, TB), ceil_div(M, TB));
   hipLaunchKernelGGL(k_gemm, grid, dim3(TB, TB), 0, s, M, N, K, A, ars, acs, B, brs, bcs, C, ldc,
                      S, lds);
+}
+
+void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const double *F,
+                     long ldf, const double *R, long rrs, long rcs, const double *S, long lds,
+                     double *C, long ldc, hipStream_t s) {
+  if (nr <= 0 || nc <= 0) return;
+  if (nr > kSandwichMax || nc > kSandwichMax)
+    throw std::runtime_error("coarse two-sided product larger than 128");
+  hipLaunchKernelGGL(k_sandwich, dim3(ceil_div(nc, 16)), dim3(512), 0, s, nr, nc, L, lrs, lcs,
+                     F, ldf, R, rrs, rcs, S, lds, C, ldc);
 }
 
 void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
@@ -349,20 +415,20 @@ void launch_convert_dot2_partials(const float *z32, double *z, const double *r, 
 }
 
 int launch_cg_update2(const double *delta, const double *pq_part, int npq, double *u,
-                      const double *p, double *r, const double *q, long n, double *rr_part,
-                      hipStream_t s, float *r32, float *z32, double *z64) {
+                      const double *p, const double *r_in, double *r_out, const double *q,
+                      long n, double *rr_part, hipStream_t s, float *r32, float *z32,
+                      double *z64) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_cg_update2, dim3(nb), dim3(RT), 0, s, delta, pq_part, npq, u, p, r, q, n,
-                     rr_part, r32, z32, z64);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb), dim3(RT), 0, s, delta, pq_part, npq, u, p, r_in,
+                     r_out, q, n, rr_part, r32, z32, z64);
   return nb;
 }
 
 void launch_cg_direction2(const double *d2_part, const double *delta, double *delta_new,
-                          double *p, const double *z, double *ro, const double *r, long n,
-                          hipStream_t s) {
+                          double *p, const double *z, long n, hipStream_t s) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_cg_direction2, dim3(nb), dim3(RT), 0, s, d2_part, nb, delta, delta_new, p,
-                     z, ro, r, n);
+                     z, n);
 }
 
 void launch_axpy(double alpha, const double *x, double *y, long n, hipStream_t s) {
