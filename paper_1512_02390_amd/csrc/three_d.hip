@@ -12,129 +12,172 @@
 namespace sem {
 namespace {
 
-// (L_1d v)(c) along one direction: sum over the (one or two) elements that
-// contain node c of (2/h_E) Lhat row (local index of c in E) . v(E's nodes);
-// v(k) reads node k.  Dirichlet lines: node n p belongs to element n-1 only.
-template <typename V>
-__device__ __forceinline__ double line_op(int c, int p, int ne, const double *Lhat, const double *s,
-                                          V v) {
-  const int e = c / p, a = c - e * p;
-  double acc = 0.0;
-  if (e < ne) {
-    const double *row = Lhat + a * (p + 1);
-    double t = 0.0;
-    for (int b = 0; b <= p; ++b) t = fma(row[b], v(e * p + b), t);
-    acc = s[e] * t;
-  }
-  if (a == 0 && e > 0) {
-    const double *row = Lhat + p * (p + 1);
-    double t = 0.0;
-    for (int b = 0; b <= p; ++b) t = fma(row[b], v((e - 1) * p + b), t);
-    acc = fma(s[e - 1], t, acc);
-  }
-  return acc;
-}
-
-// Lumped 1-D mass of node c: sum over its elements of (h/2) w.
-__device__ __forceinline__ double line_mass(int c, int p, int ne, const double *w, const double *mh) {
-  const int e = c / p, a = c - e * p;
-  double m = e < ne ? mh[e] * w[a] : 0.0;
-  if (a == 0 && e > 0) m += mh[e - 1] * w[p];
-  return m;
-}
-
-// r = f - A u (f null: r = A u), one thread per node:
-//   (A u)(k, j, i) = m_z m_y (L_x u) + m_z m_x (L_y u) + m_y m_x (L_z u).
-__global__ void k3_residual(Res3Args A) {
+// r = f - A u (f null: r = A u) by elements.  The assembled operator is the
+// sum of the element operators, each the tensor product of 1-D element
+// matrices (the 1-D assembly sums factor element by element):
+//   A_e u_e = M_z M_y (s_x Lhat) u + M_z (s_y Lhat) M_x u + (s_z Lhat) M_y M_x u
+// on the element's (p+1)^3 nodes, with the element masses (h/2) w.
+// k3_res_init sets r = f on the unknowns (0 elsewhere); k3_res_elem stages an
+// element's u in LDS and subtracts A_e u_e with atomics (adds it when f is
+// null; elements that share a node add in any order).  Lane (j, i) of the element's (p+1)^2 pencils
+// keeps its x and y operator rows and its z pencil in registers and walks the
+// pencil's layers: the x and y sums read LDS, the z sum uses the layer's
+// operator row (one row for the whole wavefront).
+__global__ void k3_res_init(Res3Args A) {
   const long n = (long)A.NX * A.NY * A.NZ;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int i = (int)(t % A.NX);
   const int j = (int)((t / A.NX) % A.NY);
   const int k = (int)(t / ((long)A.NX * A.NY));
-  if (i == 0 || j == 0 || k == 0 || i == A.NX - 1 || j == A.NY - 1 || k == A.NZ - 1) {
-    A.r[t] = 0.0;
-    return;
+  const bool in = i > 0 && j > 0 && k > 0 && i < A.NX - 1 && j < A.NY - 1 && k < A.NZ - 1;
+  A.r[t] = (in && A.f) ? A.f[t] : 0.0;
+}
+
+template <int P>
+constexpr int res3_threads() { return (P + 1) * (P + 1) <= 64 ? 64 : (P + 1) * (P + 1) <= 128 ? 128 : 256; }
+
+template <int P>
+__global__ __launch_bounds__(res3_threads<P>()) void k3_res_elem(Res3Args A) {
+  constexpr int N = P + 1, NN = N * N;
+  __shared__ double U[N * NN];
+  const long e = blockIdx.x;
+  const int ex = (int)(e % A.nx), ey = (int)((e / A.nx) % A.ny), ez = (int)(e / ((long)A.nx * A.ny));
+  const int i0 = ex * P, j0 = ey * P, k0 = ez * P;
+  for (int q = threadIdx.x; q < N * NN; q += blockDim.x) {
+    const int kk = q / NN, jj = (q / N) % N, ii = q % N;
+    const int gi = i0 + ii, gj = j0 + jj, gk = k0 + kk;
+    const bool in = gi > 0 && gj > 0 && gk > 0 && gi < A.NX - 1 && gj < A.NY - 1 && gk < A.NZ - 1;
+    U[q] = in ? A.u[((long)gk * A.NY + gj) * A.NX + gi] : 0.0;
   }
-  const long sy = A.NX, sz = (long)A.NX * A.NY;
-  const double *u = A.u;
-  const long base = t;
-  const double lx = line_op(i, A.p, A.nx, A.Lhat, A.sx, [&](int b) { return u[base - i + b]; });
-  const double ly = line_op(j, A.p, A.ny, A.Lhat, A.sy,
-                            [&](int b) { return u[base + (long)(b - j) * sy]; });
-  const double lz = line_op(k, A.p, A.nz, A.Lhat, A.sz,
-                            [&](int b) { return u[base + (long)(b - k) * sz]; });
-  const double mx = line_mass(i, A.p, A.nx, A.w, A.mx);
-  const double my = line_mass(j, A.p, A.ny, A.w, A.my);
-  const double mz = line_mass(k, A.p, A.nz, A.w, A.mz);
-  const double au = mz * my * lx + mz * mx * ly + my * mx * lz;
-  A.r[t] = A.f ? A.f[t] - au : au;
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= NN) return;   // no barrier below
+  const int jj = t / N, ii = t - (t / N) * N;
+  const int gi = i0 + ii, gj = j0 + jj;
+  const bool in_ji = gi > 0 && gj > 0 && gi < A.NX - 1 && gj < A.NY - 1;
+  double lx[N], ly[N], pz[N];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    lx[b] = A.Lhat[ii * N + b];
+    ly[b] = A.Lhat[jj * N + b];
+    pz[b] = U[(b * N + jj) * N + ii];
+  }
+  const double sx = A.sx[ex], sy = A.sy[ey], sz = A.sz[ez];
+  const double mxi = A.mx[ex] * A.w[ii], myj = A.my[ey] * A.w[jj], mz = A.mz[ez];
+  const cptr<double> Lc = as_const(A.Lhat);
+#pragma unroll
+  for (int kk = 0; kk < N; ++kk) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      ax = fma(lx[b], U[(kk * N + jj) * N + b], ax);
+      ay = fma(ly[b], U[(kk * N + b) * N + ii], ay);
+      az = fma(Lc[kk * N + b], pz[b], az);
+    }
+    const double mzk = mz * A.w[kk];
+    const double v = mzk * myj * sx * ax + mzk * mxi * sy * ay + myj * mxi * sz * az;
+    const int gk = k0 + kk;
+    if (in_ji && gk > 0 && gk < A.NZ - 1)
+      atomic_add(&A.r[((long)gk * A.NY + gj) * A.NX + gi], A.f ? -v : v);
+  }
 }
 
 // Weighted additive Schwarz correction (Algorithm 2 in 3-D): one workgroup
-// per subdomain.  The m^3 tile of r goes to LDS, the six 1-D transforms of
-// the fast diagonalisation
+// of two wavefronts per subdomain, the fast diagonalisation
 //   du = (S_z (x) S_y (x) S_x) [ (S_z (x) S_y (x) S_x)^T R / (l_z + l_y + l_x) ]
-// run along x, y, z with the subdomain type's factors, and the weighted
-// result w_z w_y w_x du is added into u (atomics: overlapping subdomains).
-constexpr int kFdm3Threads = 256;
+// as six one-axis transforms of the m^3 tile.  In each transform a lane owns
+// one pencil along the axis (m^2 pencils): it reads the pencil's m values
+// from LDS into registers and forms the m outputs as dot products with the
+// rows of the factor, which every lane of the wavefront reads at the same
+// time (scalar loads of the subdomain type's matrix).  The divide by the
+// eigenvalue sum is fused into the third transform, and the weighted result
+// w_z w_y w_x du of the sixth goes straight to u with atomics (overlapping
+// subdomains).
+constexpr int kFdm3Threads = 128;
 
-// out(k, j, i) = sum_a M(idx, a) in(... a along axis ...), M row-major m x m,
-// where idx is the output's index along the axis.
-__device__ __forceinline__ void axis_apply(const double *__restrict__ in, double *__restrict__ out,
-                                           const double *__restrict__ M, int m, int axis) {
-  const int mm = m * m, mmm = mm * m;
-  for (int t = threadIdx.x; t < mmm; t += kFdm3Threads) {
-    const int k = t / mm, j = (t / m) % m, i = t % m;
-    const int idx = axis == 0 ? i : axis == 1 ? j : k;
-    const int stride = axis == 0 ? 1 : axis == 1 ? m : mm;
-    const int base = t - idx * stride;
-    const double *row = M + idx * m;
-    double s = 0.0;
-    for (int a = 0; a < m; ++a) s = fma(row[a], in[base + a * stride], s);
-    out[t] = s;
+template <int M>
+__device__ __forceinline__ double pdot(cptr<double> row, const double (&v)[M]) {
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i + 1 < M; i += 2) {
+    a0 = fma(row[i], v[i], a0);
+    a1 = fma(row[i + 1], v[i + 1], a1);
   }
-  __syncthreads();
+  if constexpr (M % 2) a0 = fma(row[M - 1], v[M - 1], a0);
+  return a0 + a1;
 }
 
+// Element offset of tile position (k, j, i) and the pencil of lane t along
+// axis (0 x, 1 y, 2 z): base offset and stride.
+template <int M>
+__device__ __forceinline__ void pencil(int t, int axis, int &base, int &stride, int &p0, int &p1) {
+  const int hi = t / M, lo = t - (t / M) * M;
+  if (axis == 0) {          // pencil (k, j), along i
+    base = (hi * M + lo) * M;
+    stride = 1;
+  } else if (axis == 1) {   // pencil (k, i), along j
+    base = hi * M * M + lo;
+    stride = M;
+  } else {                  // pencil (j, i), along k
+    base = hi * M + lo;
+    stride = M * M;
+  }
+  p0 = hi;
+  p1 = lo;
+}
+
+template <int M>
 __global__ __launch_bounds__(kFdm3Threads) void k3_fdm(Fdm3Args A) {
-  extern __shared__ double sm3[];
-  const int m = A.m, mm = m * m, mmm = mm * m;
-  double *X = sm3, *Y = sm3 + mmm;
+  constexpr int MM = M * M, MMM = MM * M;
+  __shared__ double X[MMM], Y[MMM];
   const long s = blockIdx.x;
   const int ex = (int)(s % A.nx), ey = (int)((s / A.nx) % A.ny), ez = (int)(s / ((long)A.nx * A.ny));
   const int tx = A.tx_of[ex], ty = A.ty_of[ey], tz = A.tz_of[ez];
   const int i0 = ex * A.p - A.n_o, j0 = ey * A.p - A.n_o, k0 = ez * A.p - A.n_o;
+  const int t = threadIdx.x;
   // gather (positions that are not unknowns read zero)
-  for (int t = threadIdx.x; t < mmm; t += kFdm3Threads) {
-    const int k = t / mm, j = (t / m) % m, i = t % m;
+  for (int q = t; q < MMM; q += kFdm3Threads) {
+    const int k = q / MM, j = (q / M) % M, i = q % M;
     const int gi = i0 + i, gj = j0 + j, gk = k0 + k;
     const bool ok = gi >= 1 && gi <= A.NX - 2 && gj >= 1 && gj <= A.NY - 2 && gk >= 1 &&
                     gk <= A.NZ - 2;
-    X[t] = ok ? A.r[((long)gk * A.NY + gj) * A.NX + gi] : 0.0;
+    X[q] = ok ? A.r[((long)gk * A.NY + gj) * A.NX + gi] : 0.0;
   }
   __syncthreads();
-  const long t2 = (long)m * m;
-  axis_apply(X, Y, A.SxT + tx * t2, m, 0);   // S_x^T along x
-  axis_apply(Y, X, A.SyT + ty * t2, m, 1);   // S_y^T along y
-  axis_apply(X, Y, A.SzT + tz * t2, m, 2);   // S_z^T along z
-  const double *lx = A.lx + (long)tx * m, *ly = A.ly + (long)ty * m, *lz = A.lz + (long)tz * m;
-  for (int t = threadIdx.x; t < mmm; t += kFdm3Threads) {
-    const int k = t / mm, j = (t / m) % m, i = t % m;
-    Y[t] /= lz[k] + ly[j] + lx[i];
-  }
-  __syncthreads();
-  axis_apply(Y, X, A.Sx + tx * t2, m, 0);    // S_x along x
-  axis_apply(X, Y, A.Sy + ty * t2, m, 1);    // S_y along y
-  axis_apply(Y, X, A.Sz + tz * t2, m, 2);    // S_z along z
-  const double *wx = A.wx + (long)ex * m, *wy = A.wy + (long)ey * m, *wz = A.wz + (long)ez * m;
-  for (int t = threadIdx.x; t < mmm; t += kFdm3Threads) {
-    const int k = t / mm, j = (t / m) % m, i = t % m;
-    const int gi = i0 + i, gj = j0 + j, gk = k0 + k;
-    const bool ok = gi >= 1 && gi <= A.NX - 2 && gj >= 1 && gj <= A.NY - 2 && gk >= 1 &&
-                    gk <= A.NZ - 2;
-    if (ok) atomic_add(&A.u[((long)gk * A.NY + gj) * A.NX + gi], wz[k] * wy[j] * wx[i] * X[t]);
-  }
+  // one transform: out(pencil, o) = post(sum_a F(o, a) in(pencil, a)); the
+  // m^2 pencils over the block's lanes (more than one per lane from m = 12)
+  auto transform = [&](const double *in, double *out, const double *F, int axis, auto post) {
+    const cptr<double> Fc = as_const(F);
+    for (int q = t; q < MM; q += kFdm3Threads) {
+      int base, stride, p0, p1;
+      pencil<M>(q, axis, base, stride, p0, p1);
+      double v[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) v[a] = in[base + a * stride];
+#pragma unroll 1
+      for (int o = 0; o < M; ++o) post(base + o * stride, p0, p1, o, pdot<M>(Fc + o * M, v));
+    }
+    __syncthreads();
+  };
+  const long t2 = (long)MM;
+  auto store = [](double *dst) {
+    return [dst](int at, int, int, int, double v) { dst[at] = v; };
+  };
+  transform(X, Y, A.SxT + tx * t2, 0, store(Y));   // S_x^T along x
+  transform(Y, X, A.SyT + ty * t2, 1, store(X));   // S_y^T along y
+  const double *lx = A.lx + (long)tx * M, *ly = A.ly + (long)ty * M, *lz = A.lz + (long)tz * M;
+  transform(X, Y, A.SzT + tz * t2, 2, [&](int at, int j, int i, int k, double v) {
+    Y[at] = v / (lz[k] + ly[j] + lx[i]);           // S_z^T along z, / eigenvalue sum
+  });
+  transform(Y, X, A.Sx + tx * t2, 0, store(X));    // S_x along x
+  transform(X, Y, A.Sy + ty * t2, 1, store(Y));    // S_y along y
+  const double *wx = A.wx + (long)ex * M, *wy = A.wy + (long)ey * M, *wz = A.wz + (long)ez * M;
+  transform(Y, X, A.Sz + tz * t2, 2, [&](int, int j, int i, int k, double v) {
+    const int gi = i0 + i, gj = j0 + j, gk = k0 + k;   // S_z along z, weighted, into u
+    if (gi >= 1 && gi <= A.NX - 2 && gj >= 1 && gj <= A.NY - 2 && gk >= 1 && gk <= A.NZ - 2)
+      atomic_add(&A.u[((long)gk * A.NY + gj) * A.NX + gi], wz[k] * wy[j] * wx[i] * v);
+  });
 }
 
 // out = (accumulate ? out : 0) + band-matrix product along one axis:
@@ -195,15 +238,39 @@ inline unsigned blocks_for(long n, int b) { return (unsigned)((n + b - 1) / b); 
 void launch3_residual(const Res3Args &a, hipStream_t s) {
   const long n = (long)a.NX * a.NY * a.NZ;
   if (n <= 0) return;
-  klaunch(k3_residual, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+  if (a.p < 1 || a.p > kMaxTile3 - 1) throw std::runtime_error("3-D residual: order not in [1, 14]");
+  klaunch(k3_res_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+  const unsigned ne = (unsigned)((long)a.nx * a.ny * a.nz);
+  switch (a.p) {
+#define SEM3_RCASE(P) \
+  case P:             \
+    klaunch(k3_res_elem<P>, dim3(ne), dim3(res3_threads<P>()), 0, s, a); \
+    break;
+    SEM3_RCASE(1) SEM3_RCASE(2) SEM3_RCASE(3) SEM3_RCASE(4) SEM3_RCASE(5) SEM3_RCASE(6)
+    SEM3_RCASE(7) SEM3_RCASE(8) SEM3_RCASE(9) SEM3_RCASE(10) SEM3_RCASE(11) SEM3_RCASE(12)
+    SEM3_RCASE(13) SEM3_RCASE(14)
+#undef SEM3_RCASE
+    default:
+      break;
+  }
 }
 
 void launch3_fdm(const Fdm3Args &a, hipStream_t s) {
-  if (a.m > kMaxTile3) throw std::runtime_error("3-D Schwarz kernel: tile wider than 15");
+  if (a.m > kMaxTile3 || a.m < 2) throw std::runtime_error("3-D Schwarz kernel: tile width not in [2, 15]");
   const long ns = (long)a.nx * a.ny * a.nz;
   if (ns <= 0) return;
-  const unsigned shm = 2u * a.m * a.m * a.m * sizeof(double);
-  klaunch(k3_fdm, dim3((unsigned)ns), dim3(kFdm3Threads), shm, s, a);
+  switch (a.m) {
+#define SEM3_CASE(M) \
+  case M:            \
+    klaunch(k3_fdm<M>, dim3((unsigned)ns), dim3(kFdm3Threads), 0, s, a); \
+    break;
+    SEM3_CASE(2) SEM3_CASE(3) SEM3_CASE(4) SEM3_CASE(5) SEM3_CASE(6) SEM3_CASE(7) SEM3_CASE(8)
+    SEM3_CASE(9) SEM3_CASE(10) SEM3_CASE(11) SEM3_CASE(12) SEM3_CASE(13) SEM3_CASE(14)
+    SEM3_CASE(15)
+#undef SEM3_CASE
+    default:
+      break;
+  }
 }
 
 void launch3_axis(const Axis3Args &a, hipStream_t s) {
