@@ -66,8 +66,8 @@ struct Level3 {
   double *Lhat = nullptr, *w = nullptr;
   double *s[3] = {nullptr, nullptr, nullptr}, *mh[3] = {nullptr, nullptr, nullptr};
   Dir3 dir[3];
-  Band pro[3], res[3];    // prolongation from l-1 (rows: fine nodes), restriction (rows: coarse)
-  double *u = nullptr, *f = nullptr, *r = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *E = nullptr;    // interpolation from level l-1, (p+1) x (p_{l-1}+1)
+  double *u = nullptr, *f = nullptr, *r = nullptr;
 };
 
 }  // namespace
@@ -80,6 +80,7 @@ struct sem3_ctx {
   // coarse fast diagonalisation: per direction S (nu x nu) as bands
   Band cfwd[3], cbwd[3];       // x -> compact (S^T), compact -> node array (S)
   double *clam[3] = {nullptr, nullptr, nullptr};
+  double *cS[3] = {nullptr, nullptr, nullptr};   // dense S per direction (one-workgroup solve)
   int nu[3] = {0, 0, 0};
   double *ct1 = nullptr, *ct2 = nullptr;
   // MGCG
@@ -188,25 +189,33 @@ void smooth3(sem3_ctx *h, int l, double *u, const double *f, int n_it, bool u_is
 }
 
 // fc = I^T rf (fine level l to l-1), boundary of fc zero.
-void restrict3(sem3_ctx *h, int l, const double *rf, double *fc) {
+Transfer3Args transfer_args(sem3_ctx *h, int l, const double *in, double *out) {
   Level3 &F = h->lev[l], &C = h->lev[l - 1];
-  axis(h, F.res[0], rf, F.t1, F.N[2], F.N[1], C.N[0], 2, false, false);
-  axis(h, F.res[1], F.t1, F.t2, F.N[2], C.N[1], C.N[0], 1, false, false);
-  axis(h, F.res[2], F.t2, fc, C.N[2], C.N[1], C.N[0], 0, false, true);
+  return Transfer3Args{h->ne[0], h->ne[1], h->ne[2], F.p,   F.N[0], F.N[1], F.N[2],
+                       C.N[0],   C.N[1],   C.N[2],   F.E, in,     out};
+}
+
+void restrict3(sem3_ctx *h, int l, const double *rf, double *fc) {
+  HIP3(hipMemsetAsync(fc, 0, h->lev[l - 1].n() * sizeof(double), h->stream));
+  launch3_restrict(transfer_args(h, l, rf, fc), h->stream);
 }
 
 // uf += I uc.
 void prolong3(sem3_ctx *h, int l, const double *uc, double *uf) {
-  Level3 &F = h->lev[l], &C = h->lev[l - 1];
-  axis(h, F.pro[0], uc, F.t1, C.N[2], C.N[1], F.N[0], 2, false, false);
-  axis(h, F.pro[1], F.t1, F.t2, C.N[2], F.N[1], F.N[0], 1, false, false);
-  axis(h, F.pro[2], F.t2, uf, F.N[2], F.N[1], F.N[0], 0, true, false);
+  launch3_prolong(transfer_args(h, l, uc, uf), h->stream);
 }
 
 // u0 = A_0^{-1} f0 by global fast diagonalisation on the p = 1 level.
 void coarse3(sem3_ctx *h, const double *f0, double *u0) {
   Level3 &L = h->lev[0];
   const int *N = L.N, *n = h->nu;
+  if (n[0] >= 1 && n[1] >= 1 && n[2] >= 1 && n[0] <= kCoarse3Max && n[1] <= kCoarse3Max &&
+      n[2] <= kCoarse3Max) {
+    Coarse3Args a{{n[0], n[1], n[2]}, {N[0], N[1], N[2]}, f0, u0,
+                  {h->cS[0], h->cS[1], h->cS[2]}, {h->clam[0], h->clam[1], h->clam[2]}};
+    launch3_coarse(a, h->stream);
+    return;
+  }
   axis(h, h->cfwd[0], f0, h->ct1, N[2], N[1], n[0], 2, false, false);
   axis(h, h->cfwd[1], h->ct1, h->ct2, N[2], n[1], n[0], 1, false, false);
   axis(h, h->cfwd[2], h->ct2, h->ct1, n[2], n[1], n[0], 0, false, false);
@@ -309,21 +318,14 @@ void setup3(sem3_ctx *h, const sem_mesh3 *mesh, int p, const sem_overlap *ov, in
         lv.dir[d].wts = dev_upload(h, fd.wts);
         std::vector<int32_t> to(fd.type_of.begin(), fd.type_of.end());
         lv.dir[d].type_of = dev_upload(h, to);
-        // transfers from level l-1: dense 1-D interpolation, as bands
-        const int pc = orders[l - 1];
-        Vec xic, wc;
-        gll_rule(pc, xic, wc);
-        Mat E = lagrange_eval(xic, xi);   // (p+1) x (pc+1)
-        const int Nf = lv.N[d], Nc = ne[d] * pc + 1;
-        std::vector<double> P((size_t)Nf * Nc, 0.0), PT((size_t)Nc * Nf, 0.0);
-        for (int e = 0; e < ne[d]; ++e)
-          for (int a = 0; a <= lv.p; ++a)
-            for (int c = 0; c <= pc; ++c) P[(size_t)(e * lv.p + a) * Nc + e * pc + c] = E(a, c);
-        for (int i = 0; i < Nf; ++i)
-          for (int j = 0; j < Nc; ++j) PT[(size_t)j * Nf + i] = P[(size_t)i * Nc + j];
-        lv.pro[d] = make_band(h, P, Nf, Nc);
-        lv.res[d] = make_band(h, PT, Nc, Nf);
       }
+    }
+    if (l > 0) {
+      // transfers from level l-1: the reference interpolation E(a, c) = l_c(xi_a)
+      const int pc = orders[l - 1];
+      Vec xic, wc;
+      gll_rule(pc, xic, wc);
+      lv.E = dev_upload(h, lagrange_eval(xic, xi).a);   // (p+1) x (pc+1), row-major
     }
     const long n = lv.n();
     if (l < L) {
@@ -331,8 +333,6 @@ void setup3(sem3_ctx *h, const sem_mesh3 *mesh, int p, const sem_overlap *ov, in
       lv.f = dev_alloc<double>(h, n);
     }
     lv.r = dev_alloc<double>(h, n);
-    lv.t1 = dev_alloc<double>(h, n);
-    lv.t2 = dev_alloc<double>(h, n);
     HIP3(hipMemset(lv.r, 0, n * sizeof(double)));
   }
   // coarse fast diagonalisation (level 0, p = 1)
@@ -362,6 +362,10 @@ void setup3(sem3_ctx *h, const sem_mesh3 *mesh, int p, const sem_overlap *ov, in
       h->cfwd[d] = make_band(h, Fw, nu, N);
       h->cbwd[d] = make_band(h, Bw, N, nu);
       h->clam[d] = dev_upload(h, lam);
+      std::vector<double> Sd((size_t)nu * nu);
+      for (int a = 0; a < nu; ++a)
+        for (int o = 0; o < nu; ++o) Sd[(size_t)a * nu + o] = S(a, o);
+      h->cS[d] = dev_upload(h, Sd);
     }
     const long nc = c.n();
     h->ct1 = dev_alloc<double>(h, nc);

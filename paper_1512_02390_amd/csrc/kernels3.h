@@ -45,7 +45,37 @@ struct Axis3Args {
   int32_t accumulate, zero_bnd;
 };
 
+// Coarse solve u0 = A_0^{-1} f0 (level 0, p = 1) by global fast
+// diagonalisation in one workgroup, for nu_d <= kCoarse3Max unknowns per
+// direction: S_d (nu_d x nu_d row-major, S_d(a, o)) with S_d^T M_d S_d = I and
+// L_d S_d = M_d S_d diag(lam_d).  N[d] = nu_d + 2 nodes; u0's boundary is set
+// to zero.
+constexpr int kCoarse3Max = 18;
+struct Coarse3Args {
+  int32_t nu[3], N[3];   // x, y, z
+  const double *f0;
+  double *u0;
+  const double *S[3], *lam[3];
+};
+
+// Transfers between level l (order pf, nodes NX x NY x NZ) and level l-1
+// (order pc = ceil(pf / 2)), element by element with the reference
+// interpolation E ((pf+1) x (pc+1), E(a, c) = l_c(xi_a)).  Each fine node is
+// taken by the element that holds it at local index 0..pf-1 in every
+// direction (the last node plane of a direction is Dirichlet boundary).
+struct Transfer3Args {
+  int32_t nx, ny, nz, pf;         // elements per direction, fine order
+  int32_t NX, NY, NZ;             // fine nodes per direction
+  int32_t CX, CY, CZ;             // coarse nodes per direction
+  const double *E;
+  const double *in;               // restriction: fine r; prolongation: coarse u
+  double *out;                    // restriction: coarse f (zeroed before); prolongation: fine u (+=)
+};
+
 void launch3_residual(const Res3Args &a, hipStream_t s);
+void launch3_coarse(const Coarse3Args &a, hipStream_t s);
+void launch3_restrict(const Transfer3Args &a, hipStream_t s);
+void launch3_prolong(const Transfer3Args &a, hipStream_t s);
 void launch3_fdm(const Fdm3Args &a, hipStream_t s);
 void launch3_axis(const Axis3Args &a, hipStream_t s);
 void launch3_eig_divide(double *x, int n0, int n1, int n2, const double *lz, const double *ly,

@@ -210,6 +210,152 @@ __global__ void k3_axis(Axis3Args A) {
   A.out[t] = A.accumulate ? A.out[t] + s : s;
 }
 
+// Restriction f_c = I^T r_f by elements (Transfer3Args): the element's
+// pf^3 fine nodes go to LDS and are contracted with E along x, y, z (three
+// passes through LDS, one output per thread and step); the (pc+1)^3 results
+// are added into f_c with atomics (coarse nodes on element faces are shared).
+// A fine node on a face contributes only to the coarse nodes on that face
+// (the coarse basis vanishes there otherwise), which the element holds too.
+template <int PF>
+__global__ __launch_bounds__(256) void k3_restrict(Transfer3Args A) {
+  constexpr int PC = (PF + 1) / 2, NC = PC + 1;
+  __shared__ double R[PF * PF * PF], T1[PF * PF * NC], T2[PF * NC * NC];
+  __shared__ double E[(PF + 1) * NC];
+  const long e = blockIdx.x;
+  const int ex = (int)(e % A.nx), ey = (int)((e / A.nx) % A.ny), ez = (int)(e / ((long)A.nx * A.ny));
+  const int t = threadIdx.x;
+  for (int q = t; q < (PF + 1) * NC; q += blockDim.x) E[q] = A.E[q];
+  for (int q = t; q < PF * PF * PF; q += blockDim.x) {
+    const int a = q / (PF * PF), b = (q / PF) % PF, c = q % PF;
+    R[q] = A.in[((long)(ez * PF + a) * A.NY + ey * PF + b) * A.NX + ex * PF + c];
+  }
+  __syncthreads();
+  for (int q = t; q < PF * PF * NC; q += blockDim.x) {   // along x
+    const int ab = q / NC, cx = q % NC;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < PF; ++c) s = fma(E[c * NC + cx], R[ab * PF + c], s);
+    T1[q] = s;
+  }
+  __syncthreads();
+  for (int q = t; q < PF * NC * NC; q += blockDim.x) {   // along y
+    const int a = q / (NC * NC), cy = (q / NC) % NC, cx = q % NC;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < PF; ++b) s = fma(E[b * NC + cy], T1[(a * PF + b) * NC + cx], s);
+    T2[q] = s;
+  }
+  __syncthreads();
+  for (int q = t; q < NC * NC * NC; q += blockDim.x) {   // along z, into f_c
+    const int cz = q / (NC * NC), cy = (q / NC) % NC, cx = q % NC;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < PF; ++a) s = fma(E[a * NC + cz], T2[(a * NC + cy) * NC + cx], s);
+    const int gx = ex * PC + cx, gy = ey * PC + cy, gz = ez * PC + cz;
+    if (gx > 0 && gy > 0 && gz > 0 && gx < A.CX - 1 && gy < A.CY - 1 && gz < A.CZ - 1)
+      atomic_add(&A.out[((long)gz * A.CY + gy) * A.CX + gx], s);
+  }
+}
+
+// Prolongation u_f += I u_c by elements: the element's (pc+1)^3 coarse
+// values go to LDS and are interpolated along z, y, x onto the pf^3 fine
+// nodes the element holds, each written by exactly one element (no atomics).
+template <int PF>
+__global__ __launch_bounds__(256) void k3_prolong(Transfer3Args A) {
+  constexpr int PC = (PF + 1) / 2, NC = PC + 1;
+  __shared__ double UC[NC * NC * NC], T1[PF * NC * NC], T2[PF * PF * NC];
+  __shared__ double E[(PF + 1) * NC];
+  const long e = blockIdx.x;
+  const int ex = (int)(e % A.nx), ey = (int)((e / A.nx) % A.ny), ez = (int)(e / ((long)A.nx * A.ny));
+  const int t = threadIdx.x;
+  for (int q = t; q < (PF + 1) * NC; q += blockDim.x) E[q] = A.E[q];
+  for (int q = t; q < NC * NC * NC; q += blockDim.x) {
+    const int cz = q / (NC * NC), cy = (q / NC) % NC, cx = q % NC;
+    UC[q] = A.in[((long)(ez * PC + cz) * A.CY + ey * PC + cy) * A.CX + ex * PC + cx];
+  }
+  __syncthreads();
+  for (int q = t; q < PF * NC * NC; q += blockDim.x) {   // along z
+    const int a = q / (NC * NC), r = q % (NC * NC);
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < NC; ++cz) s = fma(E[a * NC + cz], UC[cz * NC * NC + r], s);
+    T1[q] = s;
+  }
+  __syncthreads();
+  for (int q = t; q < PF * PF * NC; q += blockDim.x) {   // along y
+    const int a = q / (PF * NC), b = (q / NC) % PF, cx = q % NC;
+    double s = 0.0;
+#pragma unroll
+    for (int cy = 0; cy < NC; ++cy) s = fma(E[b * NC + cy], T1[(a * NC + cy) * NC + cx], s);
+    T2[q] = s;
+  }
+  __syncthreads();
+  for (int q = t; q < PF * PF * PF; q += blockDim.x) {   // along x, into u_f
+    const int a = q / (PF * PF), b = (q / PF) % PF, c = q % PF;
+    double s = 0.0;
+#pragma unroll
+    for (int cx = 0; cx < NC; ++cx) s = fma(E[c * NC + cx], T2[(a * PF + b) * NC + cx], s);
+    const int gx = ex * PF + c, gy = ey * PF + b, gz = ez * PF + a;
+    if (gx > 0 && gy > 0 && gz > 0) {
+      const long node = ((long)gz * A.NY + gy) * A.NX + gx;
+      A.out[node] += s;
+    }
+  }
+}
+
+// Coarse fast diagonalisation in one workgroup (Coarse3Args): the unknowns of
+// f0 go to LDS, then three forward transforms S^T along x, y, z (the third
+// divides by l_z + l_y + l_x), and three backward transforms S along x, y, z,
+// the last one writing u0.  One output per thread and step, operands in LDS.
+__global__ __launch_bounds__(1024) void k3_coarse(Coarse3Args A) {
+  constexpr int C3 = kCoarse3Max * kCoarse3Max * kCoarse3Max;
+  __shared__ double X[C3], Y[C3];
+  __shared__ double S[3][kCoarse3Max * kCoarse3Max], lam[3][kCoarse3Max];
+  const int nx = A.nu[0], ny = A.nu[1], nz = A.nu[2];
+  const int NX = A.N[0], NY = A.N[1], NZ = A.N[2];
+  const int n = nx * ny * nz, t = threadIdx.x, nt = blockDim.x;
+  for (int d = 0; d < 3; ++d) {
+    const int m = A.nu[d];
+    for (int q = t; q < m * m; q += nt) S[d][q] = A.S[d][q];
+    for (int q = t; q < m; q += nt) lam[d][q] = A.lam[d][q];
+  }
+  for (int q = t; q < n; q += nt) {
+    const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+    X[q] = A.f0[((long)(k + 1) * NY + (j + 1)) * NX + (i + 1)];
+  }
+  __syncthreads();
+  // out(k, j, i) = sum_a F(a, idx) in(.. a ..) (forward, F = S^T) or
+  // sum_a F(idx, a) in(.. a ..) (backward, F = S), idx the output's index along axis
+  auto step = [&](const double *in, double *out, int axis, bool fwd, bool divide) {
+    const int m = A.nu[axis];
+    const double *F = S[axis];
+    for (int q = t; q < n; q += nt) {
+      const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+      const int idx = axis == 0 ? i : axis == 1 ? j : k;
+      const int stride = axis == 0 ? 1 : axis == 1 ? nx : nx * ny;
+      const int base = q - idx * stride;
+      double s = 0.0;
+      for (int a = 0; a < m; ++a)
+        s = fma(fwd ? F[a * m + idx] : F[idx * m + a], in[base + a * stride], s);
+      if (divide) s /= lam[2][k] + lam[1][j] + lam[0][i];
+      out[q] = s;
+    }
+    __syncthreads();
+  };
+  step(X, Y, 0, true, false);
+  step(Y, X, 1, true, false);
+  step(X, Y, 2, true, true);
+  step(Y, X, 0, false, false);
+  step(X, Y, 1, false, false);
+  step(Y, X, 2, false, false);
+  const long N3 = (long)NX * NY * NZ;
+  for (long q = t; q < N3; q += nt) {
+    const int i = (int)(q % NX), j = (int)((q / NX) % NY), k = (int)(q / ((long)NX * NY));
+    const bool in = i > 0 && j > 0 && k > 0 && i < NX - 1 && j < NY - 1 && k < NZ - 1;
+    A.u0[q] = in ? X[((k - 1) * ny + (j - 1)) * nx + (i - 1)] : 0.0;
+  }
+}
+
 // x /= (l_z + l_y + l_x) on the coarse unknowns' grid (n0 x n1 x n2).
 __global__ void k3_eig_divide(double *x, int n0, int n1, int n2, const double *lz, const double *ly,
                               const double *lx) {
@@ -277,6 +423,47 @@ void launch3_axis(const Axis3Args &a, hipStream_t s) {
   const long n = (long)a.d0 * a.d1 * a.d2;
   if (n <= 0) return;   // an empty axis (no coarse unknowns)
   klaunch(k3_axis, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+}
+
+void launch3_coarse(const Coarse3Args &a, hipStream_t s) {
+  for (int d = 0; d < 3; ++d)
+    if (a.nu[d] < 1 || a.nu[d] > kCoarse3Max)
+      throw std::runtime_error("3-D coarse solve: unknowns per direction not in [1, 18]");
+  klaunch(k3_coarse, dim3(1), dim3(1024), 0, s, a);
+}
+
+void launch3_restrict(const Transfer3Args &a, hipStream_t s) {
+  const unsigned ne = (unsigned)((long)a.nx * a.ny * a.nz);
+  if (ne == 0) return;
+  switch (a.pf) {
+#define SEM3_TCASE(P) \
+  case P:             \
+    klaunch(k3_restrict<P>, dim3(ne), dim3(256), 0, s, a); \
+    break;
+    SEM3_TCASE(2) SEM3_TCASE(3) SEM3_TCASE(4) SEM3_TCASE(5) SEM3_TCASE(6) SEM3_TCASE(7)
+    SEM3_TCASE(8) SEM3_TCASE(9) SEM3_TCASE(10) SEM3_TCASE(11) SEM3_TCASE(12) SEM3_TCASE(13)
+    SEM3_TCASE(14)
+#undef SEM3_TCASE
+    default:
+      throw std::runtime_error("3-D restriction: fine order not in [2, 14]");
+  }
+}
+
+void launch3_prolong(const Transfer3Args &a, hipStream_t s) {
+  const unsigned ne = (unsigned)((long)a.nx * a.ny * a.nz);
+  if (ne == 0) return;
+  switch (a.pf) {
+#define SEM3_TCASE(P) \
+  case P:             \
+    klaunch(k3_prolong<P>, dim3(ne), dim3(256), 0, s, a); \
+    break;
+    SEM3_TCASE(2) SEM3_TCASE(3) SEM3_TCASE(4) SEM3_TCASE(5) SEM3_TCASE(6) SEM3_TCASE(7)
+    SEM3_TCASE(8) SEM3_TCASE(9) SEM3_TCASE(10) SEM3_TCASE(11) SEM3_TCASE(12) SEM3_TCASE(13)
+    SEM3_TCASE(14)
+#undef SEM3_TCASE
+    default:
+      throw std::runtime_error("3-D prolongation: fine order not in [2, 14]");
+  }
 }
 
 void launch3_eig_divide(double *x, int n0, int n1, int n2, const double *lz, const double *ly,
