@@ -86,7 +86,12 @@ struct sem3_ctx {
   // MGCG
   double *r = nullptr, *ro = nullptr, *pv = nullptr, *q = nullptr, *z = nullptr;
   double *partial = nullptr, *scal = nullptr;
+  double *part_rr = nullptr, *part_d2 = nullptr;   // MGCG partial sums (device)
+  double *pin = nullptr;                           // r.r partials for the stopping test (pinned)
   std::string err;
+  ~sem3_ctx() {
+    if (pin) (void)hipHostFree(pin);
+  }
 };
 
 namespace {
@@ -379,6 +384,10 @@ void setup3(sem3_ctx *h, const sem_mesh3 *mesh, int p, const sem_overlap *ov, in
   h->z = dev_alloc<double>(h, n);
   h->partial = dev_alloc<double>(h, kRedBlocks);
   h->scal = dev_alloc<double>(h, 8);
+  h->part_rr = dev_alloc<double>(h, kRedBlocks);
+  h->part_d2 = dev_alloc<double>(h, 2 * kRedBlocks);
+  HIP3(hipHostMalloc(reinterpret_cast<void **>(&h->pin), kRedBlocks * sizeof(double),
+                     hipHostMallocDefault));
   HIP3(hipDeviceSynchronize());
 }
 
@@ -487,40 +496,49 @@ sem_status sem3_pcg_solve(sem3_handle h, double *u, const double *f, int32_t ima
     const int L = (int)h->lev.size() - 1;
     const long n = h->lev[L].n();
     const size_t bytes = n * sizeof(double);
-    auto precond = [&](const double *r, double *z) {
-      HIP3(hipMemsetAsync(z, 0, bytes, h->stream));
-      vcycle3(h, z, r, ns1, ns2);
-    };
-    residual3(h, L, u, f, h->r);
-    HIP3(hipMemsetAsync(h->ro, 0, bytes, h->stream));
-    const double r0 = std::sqrt(dot3(h, h->r, h->r, n));
+    hipStream_t st = h->stream;
+    // Algorithm 4 as in the 2-D solver: device scalars, the update fused with
+    // the r.r partials and the zero initial guess of the next cycle, the
+    // Polak-Ribiere products in one pass, one host round trip per iteration
+    // (the stopping test); r and r_old swap buffers instead of copying.
+    double *r = h->r, *ro = h->ro;
+    double *delta = h->scal + 0, *delta_next = h->scal + 1;
+    residual3(h, L, u, f, r);
+    const double r0 = std::sqrt(dot3(h, r, r, n));
     if (hist) hist[0] = r0;
+    if (!std::isfinite(r0)) throw Fail3{SEM_ENAN, "non-finite initial residual"};
     int it = 0;
     if (r0 == 0.0) {
       converged = true;
     } else {
-      precond(h->r, h->pv);
-      double delta = dot3(h, h->pv, h->r, n);
+      HIP3(hipMemsetAsync(h->pv, 0, bytes, st));
+      vcycle3(h, h->pv, r, ns1, ns2);
+      launch_dot(h->pv, r, n, h->partial, delta, st);
       for (it = 1; it <= imax; ++it) {
         residual3(h, L, h->pv, nullptr, h->q);   // q = A p
-        const double alpha = delta / dot3(h, h->pv, h->q, n);
-        launch3_axpy(u, h->pv, alpha, n, h->stream);
-        launch3_axpy(h->r, h->q, -alpha, n, h->stream);
-        const double rn = std::sqrt(dot3(h, h->r, h->r, n));
+        const int npq = launch_dot_partials(h->pv, h->q, n, h->partial, st);
+        // alpha = delta / p.q; u += alpha p; r_new = r - alpha q (into r_old's
+        // buffer); r.r partials; z = 0 for the next cycle
+        const int nrr = launch_cg_update2(delta, h->partial, npq, u, h->pv, r, ro, h->q, n,
+                                          h->part_rr, st, nullptr, nullptr, h->z);
+        std::swap(r, ro);
+        if (it == 1) HIP3(hipMemsetAsync(ro, 0, bytes, st));   // r_old starts at zero
+        HIP3(hipMemcpyAsync(h->pin, h->part_rr, nrr * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP3(hipStreamSynchronize(st));
+        double rr = 0.0;
+        for (int b = 0; b < nrr; ++b) rr += h->pin[b];
+        const double rn = std::sqrt(rr);
         if (hist) hist[it] = rn;
         if (!std::isfinite(rn)) throw Fail3{SEM_ENAN, "non-finite residual"};
         if (rn <= rtol * r0) {
           converged = true;
           break;
         }
-        precond(h->r, h->z);
-        // beta = z . (r - r_old) / delta (Polak-Ribiere)
-        const double zr = dot3(h, h->z, h->r, n);
-        const double zro = dot3(h, h->z, h->ro, n);
-        const double beta = (zr - zro) / delta;
-        launch3_xpby(h->pv, h->z, beta, n, h->stream);
-        delta = zr;
-        HIP3(hipMemcpyAsync(h->ro, h->r, bytes, hipMemcpyDeviceToDevice, h->stream));
+        vcycle3(h, h->z, r, ns1, ns2);
+        // beta = z.(r - r_old) / delta; p = z + beta p; next delta = z.r
+        launch_dot2_partials(h->z, r, ro, n, h->part_d2, st);
+        launch_cg_direction2(h->part_d2, delta, delta_next, h->pv, h->z, n, st);
+        std::swap(delta, delta_next);
       }
       if (it > imax) it = imax;
     }

@@ -72,6 +72,11 @@ struct Transfer3Args {
   double *out;                    // restriction: coarse f (zeroed before); prolongation: fine u (+=)
 };
 
+// First stage of the deterministic dot product x.y: the per-block partial
+// sums (their count is returned), added in a fixed order by the consumer.
+int launch_dot_partials(const double *x, const double *y, long n, double *partial,
+                        hipStream_t s);
+
 void launch3_residual(const Res3Args &a, hipStream_t s);
 void launch3_coarse(const Coarse3Args &a, hipStream_t s);
 void launch3_restrict(const Transfer3Args &a, hipStream_t s);

@@ -385,6 +385,13 @@ void launch_reduce(const double *partial, int nb, double *res, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, partial, nb, res);
 }
 
+int launch_dot_partials(const double *x, const double *y, long n, double *partial,
+                        hipStream_t s) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(RT), 0, s, x, y, n, partial);
+  return nb;
+}
+
 void launch_dot(const double *x, const double *y, long n, double *partial, double *res,
                 hipStream_t s) {
   const int nb = red_blocks(n);
