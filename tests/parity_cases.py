@@ -93,6 +93,9 @@ CASES = [
     Case("dir_p12_elem_varnu_stretch", 3, 4, 12, D, stretched=True, varnu=True, elem_seed=23),
     Case("dir_p16_elem_arith", 3, 3, 16, D, wf=ARITH, elem_seed=24),
     Case("dir_p32_elem", 2, 2, 32, D, elem_seed=25),
+    # wide FP64 tiles (m = 41) on meshes with several elements per type pair
+    Case("per_p32_ceil8_varnu_wide", 4, 4, 32, P, rule=CEIL8, varnu=True),
+    Case("dir_p32_ceil8_wide", 5, 2, 32, D, rule=CEIL8),
     # separable local coefficients per subdomain (variable nu)
     Case("dir_p8_sep_stretch", 5, 4, 8, D, stretched=True, rule=CEIL8, varnu=True,
          separable=True),
