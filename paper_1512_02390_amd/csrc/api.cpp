@@ -219,6 +219,7 @@ struct sem_ctx {
   int cnx = 0, cny = 0;           // unknowns per direction on level 0
   long coff = 0;                  // offset of the unknown block in the node array
   double *cSx = nullptr, *cSy = nullptr, *cDinv = nullptr, *cT1 = nullptr, *cT2 = nullptr;
+  double *cSxT = nullptr, *cSyT = nullptr;   // transposes (coalesced operands of k_sandwich)
   double *cMinv = nullptr;        // dense inverse (variable nu)
   double *cf = nullptr;           // projected copy of f0 (periodic)
   double *cu64 = nullptr, *cf64 = nullptr;  // FP64 coarse vectors for the FP32 cycle
@@ -988,6 +989,14 @@ void setup_impl(sem_ctx *h, const sem_mesh *mesh, int p, const sem_overlap *ov,
         }
       h->cSx = upload<double>(h->pool, Sx);
       h->cSy = upload<double>(h->pool, Sy);
+      auto transpose = [](const std::vector<double> &A, int n) {
+        std::vector<double> T(A.size());
+        for (int a = 0; a < n; ++a)
+          for (int b = 0; b < n; ++b) T[(size_t)b * n + a] = A[(size_t)a * n + b];
+        return T;
+      };
+      h->cSxT = upload<double>(h->pool, transpose(Sx, h->cnx));
+      h->cSyT = upload<double>(h->pool, transpose(Sy, h->cny));
       h->cDinv = upload<double>(h->pool, Dv);
       h->cT1 = dalloc<double>(h->pool, (size_t)h->cnx * h->cny);
       h->cT2 = dalloc<double>(h->pool, (size_t)h->cnx * h->cny);
@@ -1185,9 +1194,11 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0, bool u0_clear = fa
     launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
   } else if (nx <= kSandwichMax && ny <= kSandwichMax) {
     // T2 = (S_y^T F S_x) .* Dinv ; U = S_y T2 S_x^T, one launch each
+    // L(i, k) = S_y(k, i) read from S_y itself (lrs = 1); S_y and S_x^T read
+    // through the stored transposes, so that every operand read is coalesced
     launch_sandwich(ny, nx, h->cSy, 1, ny, f + h->coff, ld, h->cSx, nx, 1, h->cDinv, nx, h->cT2,
                     nx, s);
-    launch_sandwich(ny, nx, h->cSy, ny, 1, h->cT2, nx, h->cSx, 1, nx, nullptr, 0, u0 + h->coff,
+    launch_sandwich(ny, nx, h->cSyT, 1, ny, h->cT2, nx, h->cSxT, nx, 1, nullptr, 0, u0 + h->coff,
                     ld, s);
   } else {
     // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T

@@ -41,13 +41,15 @@ __global__ void k_gemm(int M, int N, int K, const double *__restrict__ A, long a
 
 // ---------------------------------------------------------------------------
 // Two-sided product C = S .* (L F R) for the coarse fast diagonalisation, one
-// launch instead of two GEMMs.  One block of 8 wavefronts per 16-column strip
-// of C: wavefront w forms rows [16 w, 16 w + 16) of G = F R(:, strip) with the
+// launch instead of two GEMMs.  One block of 8 wavefronts per 16-row strip of
+// C: wavefront w forms columns [16 w, 16 w + 16) of G = L(strip, :) F with the
 // FP64 matrix-core product v_mfma_f64_16x16x4 (A 16x4: lane i + 16 k holds
 // A(i, k); B 4x16: lane j + 16 k holds B(k, j); the 16x16 result: lane
-// j + 16 g holds rows g, g + 4, g + 8, g + 12 of column j), keeps G in LDS, then forms
-// the same rows of L G.  All operand loads of both products are issued
-// before the first product.
+// j + 16 g holds rows g, g + 4, g + 8, g + 12 of column j), keeps the strip of
+// G in LDS, then forms the same columns of G R.  The B operands are rows of F
+// and R, read 16 consecutive values at a time; L is read through its
+// transpose (lrs = 1 reads it coalesced too).  All operand loads of the
+// first product are issued before it.
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kSwSteps = kSandwichMax / 4;   // k steps of 4
@@ -57,38 +59,43 @@ __global__ __launch_bounds__(512) void k_sandwich(int nr, int nc, const double *
                                                   long ldf, const double *__restrict__ R, long rrs,
                                                   long rcs, const double *__restrict__ S,
                                                   long lds_, double *__restrict__ C, long ldc) {
-  __shared__ double G[kSandwichMax][17];
+  __shared__ double G[16][kSandwichMax + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
-  const int row = w * 16 + i;          // A-operand row of this lane
-  const int col = blockIdx.x * 16 + i; // B-operand column of this lane (first product)
-  double a1[kSwSteps], b1[kSwSteps], a2[kSwSteps];
+  const int row = blockIdx.x * 16 + i;   // strip row of this lane's A operand
+  const int col = w * 16 + i;            // column of this lane's B operands
+  double a1[kSwSteps], b1[kSwSteps];
 #pragma unroll
   for (int t = 0; t < kSwSteps; ++t) {
     const int k = 4 * t + kq;
-    a1[t] = (row < nr && k < nc) ? F[(long)row * ldf + k] : 0.0;
-    b1[t] = (k < nc && col < nc) ? R[(long)k * rrs + (long)col * rcs] : 0.0;
-    a2[t] = (row < nr && k < nr) ? L[(long)row * lrs + (long)k * lcs] : 0.0;
+    a1[t] = (row < nr && k < nr) ? L[(long)row * lrs + (long)k * lcs] : 0.0;
+    b1[t] = (k < nr && col < nc) ? F[(long)k * ldf + col] : 0.0;
   }
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < kSwSteps; ++t)
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1[t], acc, 0, 0, 0);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) G[w * 16 + kq + 4 * r][i] = acc[r];
+  for (int r = 0; r < 4; ++r) G[kq + 4 * r][col] = acc[r];
+  // the second product's B operands, loaded while the strip is completed
+  double b2[kSwSteps];
+#pragma unroll
+  for (int t = 0; t < kSwSteps; ++t) {
+    const int k = 4 * t + kq;
+    b2[t] = (k < nc && col < nc) ? R[(long)k * rrs + (long)col * rcs] : 0.0;
+  }
   __syncthreads();
   dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < kSwSteps; ++t)
-    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[t], G[4 * t + kq][i], acc2, 0, 0, 0);
-  const int cj = blockIdx.x * 16 + i;
+    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(G[i][4 * t + kq], b2[t], acc2, 0, 0, 0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int ci = w * 16 + kq + 4 * r;
-    if (ci < nr && cj < nc) {
+    const int ci = blockIdx.x * 16 + kq + 4 * r;
+    if (ci < nr && col < nc) {
       double v = acc2[r];
-      if (S) v *= S[(long)ci * lds_ + cj];
-      C[(long)ci * ldc + cj] = v;
+      if (S) v *= S[(long)ci * lds_ + col];
+      C[(long)ci * ldc + col] = v;
     }
   }
 }
@@ -338,7 +345,7 @@ void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const 
   if (nr <= 0 || nc <= 0) return;
   if (nr > kSandwichMax || nc > kSandwichMax)
     throw std::runtime_error("coarse two-sided product larger than 128");
-  hipLaunchKernelGGL(k_sandwich, dim3(ceil_div(nc, 16)), dim3(512), 0, s, nr, nc, L, lrs, lcs,
+  hipLaunchKernelGGL(k_sandwich, dim3(ceil_div(nr, 16)), dim3(512), 0, s, nr, nc, L, lrs, lcs,
                      F, ldf, R, rrs, rcs, S, lds, C, ldc);
 }
 
