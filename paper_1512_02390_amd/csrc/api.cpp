@@ -1191,15 +1191,15 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0, bool u0_clear = fa
   }
   if (!u0_clear) launch_fill<double>(u0, c.n(), 0.0, s);
   if (h->cMinv) {
-    launch_dense_matvec(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
+    launch_dense_matvec<double>(nx * ny, h->cMinv, f, h->coff, (int)ld, nx, u0, s);
   } else if (nx <= kSandwichMax && ny <= kSandwichMax) {
     // T2 = (S_y^T F S_x) .* Dinv ; U = S_y T2 S_x^T, one launch each
     // L(i, k) = S_y(k, i) read from S_y itself (lrs = 1); S_y and S_x^T read
     // through the stored transposes, so that every operand read is coalesced
-    launch_sandwich(ny, nx, h->cSy, 1, ny, f + h->coff, ld, h->cSx, nx, 1, h->cDinv, nx, h->cT2,
-                    nx, s);
-    launch_sandwich(ny, nx, h->cSyT, 1, ny, h->cT2, nx, h->cSxT, nx, 1, nullptr, 0, u0 + h->coff,
-                    ld, s);
+    launch_sandwich<double, double>(ny, nx, h->cSy, 1, ny, f + h->coff, ld, h->cSx, nx, 1,
+                                    h->cDinv, nx, h->cT2, nx, s);
+    launch_sandwich<double, double>(ny, nx, h->cSyT, 1, ny, h->cT2, nx, h->cSxT, nx, 1, nullptr,
+                                    0, u0 + h->coff, ld, s);
   } else {
     // T1 = S_y^T F ; T2 = (T1 S_x) .* Dinv ; T3 = S_y T2 ; U = T3 S_x^T
     launch_gemm(ny, nx, ny, h->cSy, 1, ny, f + h->coff, ld, 1, h->cT1, nx, nullptr, 0, s);
@@ -1216,11 +1216,31 @@ void coarse_solve64(sem_ctx *h, const double *f0, double *u0, bool u0_clear = fa
 void coarse_solve(sem_ctx *h, const double *f0, double *u0, bool u0_clear) {
   coarse_solve64(h, f0, u0, u0_clear);
 }
-void coarse_solve(sem_ctx *h, const float *f0, float *u0, bool) {
-  const long n = h->lev[0].n();
-  launch_convert<float, double>(f0, h->cf64, n, 1.0, h->stream);
+// The FP32 cycle's coarse solve: FP64 arithmetic read from and written to the
+// FP32 arrays directly where the problem has no mean to project out; through
+// FP64 copies otherwise.
+void coarse_solve(sem_ctx *h, const float *f0, float *u0, bool u0_clear) {
+  Level &c = h->lev[0];
+  hipStream_t s = h->stream;
+  const long n = c.n(), ld = c.g.cols;
+  const int nx = h->cnx, ny = h->cny;
+  const bool direct = !c.g.periodic && nx > 0 && ny > 0 &&
+                      (h->cMinv || (nx <= kSandwichMax && ny <= kSandwichMax));
+  if (direct) {
+    if (!u0_clear) launch_fill<float>(u0, n, 0.0f, s);
+    if (h->cMinv) {
+      launch_dense_matvec<float>(nx * ny, h->cMinv, f0, h->coff, (int)ld, nx, u0, s);
+    } else {
+      launch_sandwich<float, double>(ny, nx, h->cSy, 1, ny, f0 + h->coff, ld, h->cSx, nx, 1,
+                                     h->cDinv, nx, h->cT2, nx, s);
+      launch_sandwich<double, float>(ny, nx, h->cSyT, 1, ny, h->cT2, nx, h->cSxT, nx, 1, nullptr,
+                                     0, u0 + h->coff, ld, s);
+    }
+    return;
+  }
+  launch_convert<float, double>(f0, h->cf64, n, 1.0, s);
   coarse_solve64(h, h->cf64, h->cu64);
-  launch_convert<double, float>(h->cu64, u0, n, 1.0, h->stream);
+  launch_convert<double, float>(h->cu64, u0, n, 1.0, s);
 }
 
 template <typename T>
@@ -1260,10 +1280,9 @@ void vcycle_impl(sem_ctx *h, T *uL, const T *fL, const int32_t *ns1, const int32
     }
     Level &cl = h->lev[l - 1];
     T *fc = V::f(cl);
-    // the restriction also clears the next level's correction (for level 0
-    // only in FP64: the FP32 cycle solves the coarse problem in an FP64 copy)
-    const bool clear = l - 1 > 0 || std::is_same<T, double>::value;
-    restrict_<T>(h, l, rr, fc, clear ? V::u(cl) : nullptr);
+    // the restriction also clears the next level's correction (level 0
+    // included: the coarse solve then writes only the unknowns)
+    restrict_<T>(h, l, rr, fc, V::u(cl));
     f[l - 1] = fc;
   }
   // with a single level (p = 1) the cycle is the coarse solve on the caller's array

@@ -151,14 +151,19 @@ void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const
 // C (nr x nc) = S .* (L F R) in one launch, for nr, nc <= kSandwichMax: L is
 // nr x nr with element (i, k) at L[i lrs + k lcs], F nr x nc with leading
 // dimension ldf, R nc x nc with element (k, j) at R[k rrs + j rcs]; S (null:
-// no scaling) and C with leading dimensions lds and ldc.
+// no scaling) and C with leading dimensions lds and ldc.  F and C may be
+// FP32 arrays (instantiated: double/double, float/double, double/float); the
+// arithmetic is FP64.
 constexpr int kSandwichMax = 128;
-void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const double *F,
-                     long ldf, const double *R, long rrs, long rcs, const double *S, long lds,
-                     double *C, long ldc, hipStream_t s);
-// y = Minv x on the unknown block of a node array (dense inverse, var nu).
-void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
-                         int nux, double *y, hipStream_t s);
+template <typename TF, typename TC>
+void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const TF *F, long ldf,
+                     const double *R, long rrs, long rcs, const double *S, long lds, TC *C,
+                     long ldc, hipStream_t s);
+// y = Minv x on the unknown block of a node array (dense inverse, var nu);
+// x and y FP64 or FP32, the arithmetic FP64.
+template <typename T>
+void launch_dense_matvec(int n, const double *Minv, const T *x, long xoff, int xcols, int nux,
+                         T *y, hipStream_t s);
 
 // Vector helpers over whole node arrays of n entries.
 template <typename T>

@@ -54,11 +54,14 @@ __global__ void k_gemm(int M, int N, int K, const double *__restrict__ A, long a
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kSwSteps = kSandwichMax / 4;   // k steps of 4
 
+// TF, TC: element types of F and C (FP32 arrays of the mixed-precision cycle
+// are read and written directly; the arithmetic is FP64).
+template <typename TF, typename TC>
 __global__ __launch_bounds__(512) void k_sandwich(int nr, int nc, const double *__restrict__ L,
-                                                  long lrs, long lcs, const double *__restrict__ F,
+                                                  long lrs, long lcs, const TF *__restrict__ F,
                                                   long ldf, const double *__restrict__ R, long rrs,
                                                   long rcs, const double *__restrict__ S,
-                                                  long lds_, double *__restrict__ C, long ldc) {
+                                                  long lds_, TC *__restrict__ C, long ldc) {
   __shared__ double G[16][kSandwichMax + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(512) void k_sandwich(int nr, int nc, const double *
   for (int t = 0; t < kSwSteps; ++t) {
     const int k = 4 * t + kq;
     a1[t] = (row < nr && k < nr) ? L[(long)row * lrs + (long)k * lcs] : 0.0;
-    b1[t] = (k < nr && col < nc) ? F[(long)k * ldf + col] : 0.0;
+    b1[t] = (k < nr && col < nc) ? (double)F[(long)k * ldf + col] : 0.0;
   }
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -95,22 +98,23 @@ __global__ __launch_bounds__(512) void k_sandwich(int nr, int nc, const double *
     if (ci < nr && col < nc) {
       double v = acc2[r];
       if (S) v *= S[(long)ci * lds_ + col];
-      C[(long)ci * ldc + col] = v;
+      C[(long)ci * ldc + col] = (TC)v;
     }
   }
 }
 
 // y[unknown i] = sum_j Minv[i][j] x[unknown j]; unknowns form an nux-wide
 // block starting at xoff of a node array with xcols columns.
+template <typename T>
 __global__ void k_dense_matvec(int n, const double *__restrict__ Minv,
-                               const double *__restrict__ x, long xoff, int xcols, int nux,
-                               double *__restrict__ y) {
+                               const T *__restrict__ x, long xoff, int xcols, int nux,
+                               T *__restrict__ y) {
   __shared__ double red[256];
   const int i = blockIdx.x;
   double s = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const int jr = j / nux, jc = j - jr * nux;
-    s = fma(Minv[(long)i * n + j], x[xoff + (long)jr * xcols + jc], s);
+    s = fma(Minv[(long)i * n + j], (double)x[xoff + (long)jr * xcols + jc], s);
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -120,7 +124,7 @@ __global__ void k_dense_matvec(int n, const double *__restrict__ Minv,
   }
   if (threadIdx.x == 0) {
     const int ir = i / nux, ic = i - ir * nux;
-    y[xoff + (long)ir * xcols + ic] = red[0];
+    y[xoff + (long)ir * xcols + ic] = (T)red[0];
   }
 }
 
@@ -339,20 +343,36 @@ void launch_gemm(int M, int N, int K, const double *A, long ars, long acs, const
                      S, lds);
 }
 
-void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const double *F,
-                     long ldf, const double *R, long rrs, long rcs, const double *S, long lds,
-                     double *C, long ldc, hipStream_t s) {
+template <typename TF, typename TC>
+void launch_sandwich(int nr, int nc, const double *L, long lrs, long lcs, const TF *F, long ldf,
+                     const double *R, long rrs, long rcs, const double *S, long lds, TC *C,
+                     long ldc, hipStream_t s) {
   if (nr <= 0 || nc <= 0) return;
   if (nr > kSandwichMax || nc > kSandwichMax)
     throw std::runtime_error("coarse two-sided product larger than 128");
-  hipLaunchKernelGGL(k_sandwich, dim3(ceil_div(nr, 16)), dim3(512), 0, s, nr, nc, L, lrs, lcs,
-                     F, ldf, R, rrs, rcs, S, lds, C, ldc);
+  hipLaunchKernelGGL((k_sandwich<TF, TC>), dim3(ceil_div(nr, 16)), dim3(512), 0, s, nr, nc, L,
+                     lrs, lcs, F, ldf, R, rrs, rcs, S, lds, C, ldc);
 }
+template void launch_sandwich<double, double>(int, int, const double *, long, long,
+                                              const double *, long, const double *, long, long,
+                                              const double *, long, double *, long, hipStream_t);
+template void launch_sandwich<float, double>(int, int, const double *, long, long, const float *,
+                                             long, const double *, long, long, const double *,
+                                             long, double *, long, hipStream_t);
+template void launch_sandwich<double, float>(int, int, const double *, long, long,
+                                             const double *, long, const double *, long, long,
+                                             const double *, long, float *, long, hipStream_t);
 
-void launch_dense_matvec(int n, const double *Minv, const double *x, long xoff, int xcols,
-                         int nux, double *y, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_matvec, dim3(n), dim3(256), 0, s, n, Minv, x, xoff, xcols, nux, y);
+template <typename T>
+void launch_dense_matvec(int n, const double *Minv, const T *x, long xoff, int xcols, int nux,
+                         T *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_dense_matvec<T>), dim3(n), dim3(256), 0, s, n, Minv, x, xoff, xcols, nux,
+                     y);
 }
+template void launch_dense_matvec<double>(int, const double *, const double *, long, int, int,
+                                          double *, hipStream_t);
+template void launch_dense_matvec<float>(int, const double *, const float *, long, int, int,
+                                         float *, hipStream_t);
 
 template <typename T>
 void launch_mass(const Grid &g, const T *f, T *b, const T *w, const T *mx, const T *my,
