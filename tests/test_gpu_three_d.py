@@ -3,7 +3,8 @@ seeded inputs, element by element, FP64 tolerance 1e-12 relative to the
 largest entry: residual and operator, Schwarz sweeps, transfers, coarse
 solve, V-cycles and the MGCG solve (iterations equal, history and solution
 to 1e-12).  Cases: uniform and stretched meshes, fixed and ceil(p_l/8)
-overlaps, n_o = 0, quintic, cubic and top-hat weights, a single element."""
+overlaps, n_o = 0, quintic, cubic and top-hat weights, a single element, and
+a coarse grid too long for the one-workgroup coarse solve."""
 from dataclasses import dataclass
 
 import numpy as np
@@ -41,6 +42,9 @@ CASES3 = [
     Case3("p8_ceil8_stretch", (2, 2, 3), 8, rule=1, stretched=True),
     Case3("p5_no0_tophat", (2, 2, 2), 5, n_o=0, wf=-1),
     Case3("p7_single_element", (1, 1, 1), 7, n_o=3),
+    # 20 elements along x: 19 coarse unknowns, beyond the one-workgroup coarse
+    # solve (band products along each axis instead)
+    Case3("p2_no1_long_x", (20, 2, 2), 2),
 ]
 
 
