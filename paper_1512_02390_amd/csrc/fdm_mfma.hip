@@ -65,6 +65,13 @@ struct OpF16 {
   }
 };
 
+// a[i] through a 32-bit byte offset from the array's base (arrays below 2^30
+// words): the load then takes the base from scalar registers and the offset
+// from one vector register, instead of a 64-bit address per load.
+__device__ __forceinline__ float ld_off(const float *__restrict__ a, unsigned i) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a) + (i << 2));
+}
+
 // Largest magnitude over the wavefront's NB x NB accumulator blocks.
 template <int NB>
 __device__ __forceinline__ float wave_amax(const f32x4 (&Y)[NB][NB]) {
@@ -114,25 +121,34 @@ __device__ __forceinline__ void to_operands(const f32x4 (&Y)[NB][NB],
     }
 }
 
-// Y = X^T B block by block: Y[I][J] = sum_c Xa[c][I] B[c][J], the B blocks of
-// one output column loaded just before use (lane's 16 bytes of each).
+typedef const uint4 __attribute__((address_space(1))) *gptr4;
+
+// The lane's B operands of one factor matrix: KC x NB blocks, 16 bytes each
+// (through a global-space pointer: the operand tables are device memory).
+template <class Op, int NB>
+__device__ __forceinline__ void load_operands(gptr4 B, int lane,
+                                              typename Op::v8 (&b)[(NB + 1) / 2][NB]) {
+#pragma unroll
+  for (int c = 0; c < (NB + 1) / 2; ++c)
+#pragma unroll
+    for (int J = 0; J < NB; ++J) b[c][J] = __builtin_bit_cast(typename Op::v8, B[(c * NB + J) * 64 + lane]);
+}
+
+// Y = X^T B block by block: Y[I][J] = sum_c Xa[c][I] b[c][J].
 template <class Op, int NB>
 __device__ __forceinline__ void product(const typename Op::v8 (&Xa)[(NB + 1) / 2][NB],
-                                        const uint4 *__restrict__ B, int lane, f32x4 (&Y)[NB][NB]) {
+                                        const typename Op::v8 (&b)[(NB + 1) / 2][NB],
+                                        f32x4 (&Y)[NB][NB]) {
   constexpr int KC = (NB + 1) / 2;
 #pragma unroll
-  for (int J = 0; J < NB; ++J) {
-    typename Op::v8 b[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) b[c] = __builtin_bit_cast(typename Op::v8, B[(c * NB + J) * 64 + lane]);
+  for (int J = 0; J < NB; ++J)
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int c = 0; c < KC; ++c) acc = Op::mma(Xa[c][I], b[c], acc);
+      for (int c = 0; c < KC; ++c) acc = Op::mma(Xa[c][I], b[c][J], acc);
       Y[I][J] = acc;
     }
-  }
 }
 
 template <class Op, int NB>
@@ -142,61 +158,72 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NB > 2 ? 3 :
   constexpr int MAT = KC * NB * 64;   // uint4 per operand matrix
   const FdmTask *__restrict__ task = A.tasks + blockIdx.x;
   const int ty = task->ty, tx = task->tx, cnt = task->count;
-  const int m = A.m;
-  const int lane = threadIdx.x;
-  const int c16 = lane & 15;        // column within a block
-  const int r4 = (lane >> 4) * 4;   // first of the lane's 4 rows within a block
+  const int lane0 = threadIdx.x;
   const Grid g = A.g;
   const int per = g.periodic;
   const uint4 *__restrict__ By = A.mo.by + (long)ty * 2 * MAT;   // S_y, (W_y S_y)^T
   const uint4 *__restrict__ Bx = A.mo.bx + (long)tx * 2 * MAT;   // S_x, S_x^T
   const int Ef = A.mo.ey[2 * ty] + A.mo.ey[2 * ty + 1] + A.mo.ex[2 * tx] + A.mo.ex[2 * tx + 1];
   // 1 / (lambda_y + lambda_x) of the type pair, read in accumulator layout
-  // where it is applied (cached: every element of the work item uses it)
-  const float *__restrict__ dv = A.dinv + ((long)ty * A.ntx + tx) * m * m;
+  // with every element's gather (cached: all elements of the work item use it)
+  const float *__restrict__ dv = A.dinv + ((long)ty * A.ntx + tx) * A.m * A.m;
 
   constexpr int N = 16 * NB;   // padded tile width
   constexpr int LS = 65;        // LDS row stride: one word per lane, plus one
   __shared__ float tile[N * LS];
+  // Memory round trips, not the matrix cores, set the time of a work item:
+  // every load whose address is known is issued in one batch, and the
+  // scheduling barriers keep the compiler from interleaving the batch with
+  // its uses (which would wait on the loads one by one).  Narrow tiles hold
+  // all four factor operands for the whole work item; wide ones load the
+  // first two with the gather and the others after the first and second
+  // products (the register budget of three wavefronts per SIMD).
+  constexpr bool kHoldAll = NB <= 2;
+  v8 b1[KC][NB], b2[KC][NB], b3[KC][NB], b4[KC][NB];
+  if constexpr (kHoldAll) {
+    load_operands<Op, NB>((gptr4)By, lane0, b1);          // S_y
+    load_operands<Op, NB>((gptr4)Bx, lane0, b2);          // S_x
+    load_operands<Op, NB>((gptr4)By + MAT, lane0, b3);    // (W_y S_y)^T
+    load_operands<Op, NB>((gptr4)Bx + MAT, lane0, b4);    // S_x^T
+  }
   for (int e = 0; e < cnt; ++e) {
-    // (the address passes an optimisation barrier so that the tile is not
-    // hoisted out of the element loop into registers)
-    const float *__restrict__ dve = opaque(dv);
-    // wide tiles also reload the factor operands per element (24 of them
-    // would otherwise stay in registers across the loop)
-    const uint4 *__restrict__ Bye = NB > 2 ? opaque(By) : By;
-    const uint4 *__restrict__ Bxe = NB > 2 ? opaque(Bx) : Bx;
+    // The tile width, the lane index and the wide tiles' operand addresses
+    // pass an optimisation barrier: otherwise the compiler hoists the
+    // element-independent index arithmetic and loads out of the loop and
+    // keeps them (or their spill slots) live across it.
+    int m = A.m, lane = lane0;
+    asm volatile("" : "+s"(m));
+    asm volatile("" : "+v"(lane));
+    const int c16 = lane & 15;        // column within a block
+    const int r4 = (lane >> 4) * 4;   // first of the lane's 4 rows within a block
+    const gptr4 Bye = (gptr4)(kHoldAll ? By : opaque(By));
+    const gptr4 Bxe = (gptr4)(kHoldAll ? Bx : opaque(Bx));
     const int packed = task->elem[e];
     const int ey = packed >> 16, ex = packed & 0xffff;
     const int row0 = ey * g.p - A.n_o, col0 = ex * g.p - A.n_o;
     const float s = A.nuinv ? A.nuinv[(long)ey * g.nx + ex] : 1.0f;
-    // gather R straight into accumulator layout (block (K, I) holds rows
-    // 16K + r4 + j, columns 16I + c16 of the tile), fully unrolled so that
-    // every load is in flight together.  Addresses are wrapped (periodic) or
-    // clamped into the array (Dirichlet), so every load is valid; positions
-    // that are padding or not unknowns are then zeroed by 0/1 factors held
-    // in registers (selects would keep one lane mask per position alive
-    // across the loads).  32-bit node offsets (arrays below 2^32 words) let
-    // every load take the array base from scalar registers.
-    float rowf[NB][4], colf[NB];
+    if constexpr (!kHoldAll) {
+      load_operands<Op, NB>(Bye, lane, b1);
+      load_operands<Op, NB>(Bxe, lane, b2);
+    }
+    // R in accumulator layout (block (K, I) holds rows 16K + r4 + j, columns
+    // 16I + c16 of the tile).  Addresses are wrapped (periodic) or clamped
+    // into the array (Dirichlet), so every load is valid; padding and
+    // positions that are not unknowns are zeroed afterwards by 0/1 factors.
     int growv[NB][4], gcolv[NB];
 #pragma unroll
     for (int K = 0; K < NB; ++K)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int a = 16 * K + r4 + j;
-        const int rr = row0 + a;
+        const int rr = row0 + 16 * K + r4 + j;
         const int rw = rr < 0 ? rr + g.rows : (rr >= g.rows ? rr - g.rows : rr);
         growv[K][j] = per ? rw : min(max(rr, 0), g.rows - 1);
-        rowf[K][j] = (a < m && (per || (rr >= 1 && rr <= g.rows - 2))) ? 1.f : 0.f;
       }
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
-      const int n = 16 * I + c16;
-      const int cc = col0 + n;
+      const int cc = col0 + 16 * I + c16;
       const int cw = cc < 0 ? cc + g.cols : (cc >= g.cols ? cc - g.cols : cc);
       gcolv[I] = per ? cw : min(max(cc, 0), g.cols - 1);
-      colf[I] = (n < m && (per || (cc >= 1 && cc <= g.cols - 2))) ? 1.f : 0.f;
     }
     f32x4 Y[NB][NB];
 #pragma unroll
@@ -204,29 +231,65 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NB > 2 ? 3 :
 #pragma unroll
       for (int I = 0; I < NB; ++I)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          Y[K][I][j] = A.r[(unsigned)(growv[K][j] * g.cols + gcolv[I])] * (rowf[K][j] * colf[I]);
+        for (int j = 0; j < 4; ++j) Y[K][I][j] = ld_off(A.r, (unsigned)(growv[K][j] * g.cols + gcolv[I]));
+    // D_s / nu_bar in accumulator layout (indices clamped into the m x m
+    // tile, padding zeroed where it is applied): narrow tiles load it with
+    // the gather, wide ones after the second product
+    float dv4[NB][NB][4];
+    auto load_dv = [&]() {
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            dv4[I][J][j] = ld_off(dv, (unsigned)(min(16 * I + r4 + j, m - 1) * m + min(16 * J + c16, m - 1)));
+    };
+    if constexpr (kHoldAll) load_dv();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int K = 0; K < NB; ++K)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = 16 * K + r4 + j, rr = row0 + a;
+        const float rf = ((a < m) & (per | ((rr >= 1) & (rr <= g.rows - 2)))) ? 1.f : 0.f;
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+          const int n = 16 * I + c16, cc = col0 + n;
+          const float cf = ((n < m) & (per | ((cc >= 1) & (cc <= g.cols - 2)))) ? 1.f : 0.f;
+          Y[K][I][j] *= rf * cf;
+        }
+      }
     int E = Ef;   // du = 2^E times the last accumulator (scaled operands)
     v8 Xa[KC][NB];
     to_operands<Op, NB>(Y, Xa, E);
-    product<Op, NB>(Xa, Bye, lane, Y);         // P1^T = R^T S_y
+    product<Op, NB>(Xa, b1, Y);                   // P1^T = R^T S_y
+    if constexpr (!kHoldAll) {
+      load_operands<Op, NB>(Bye + MAT, lane, b3);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     to_operands<Op, NB>(Y, Xa, E);
-    product<Op, NB>(Xa, Bxe, lane, Y);         // P2 = P1 S_x
+    product<Op, NB>(Xa, b2, Y);                   // P2 = P1 S_x
+    if constexpr (!kHoldAll) {
+      load_dv();
+      load_operands<Op, NB>(Bxe + MAT, lane, b4);
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
-      for (int J = 0; J < NB; ++J) {                          // .* D_s / nu_bar
+      for (int J = 0; J < NB; ++J) {              // .* D_s / nu_bar
         const int n = 16 * J + c16;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = 16 * I + r4 + j;
-          Y[I][J][j] *= (k < m && n < m) ? dve[k * m + n] * s : 0.f;
+          Y[I][J][j] *= ((k < m) & (n < m)) ? dv4[I][J][j] * s : 0.f;
         }
       }
     to_operands<Op, NB>(Y, Xa, E);
-    product<Op, NB>(Xa, Bye + MAT, lane, Y);   // Q^T = P2^T (W_y S_y)^T
+    product<Op, NB>(Xa, b3, Y);                   // Q^T = P2^T (W_y S_y)^T
     to_operands<Op, NB>(Y, Xa, E);
-    product<Op, NB>(Xa, Bxe + MAT, lane, Y);   // du = Q S_x^T
+    product<Op, NB>(Xa, b4, Y);                   // du = Q S_x^T
     const float back = Op::kScaled ? ldexpf(1.f, E) : 1.f;
     const float *__restrict__ we = A.wel ? A.wel + ((long)ey * g.nx + ex) * 2 * m : nullptr;
     // weighted scatter-add through LDS: the accumulators go back to the tile,
@@ -248,16 +311,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NB > 2 ? 3 :
         float cv[RB];
 #pragma unroll
         for (int t = 0; t < RB; ++t) cv[t] = tile[(a0 + t) * LS + lane] * wxn;   // rows < N
+        if (we) {
+          // per-element weights: the row weights and the normalisation of
+          // the RB nodes loaded together (clamped addresses, unused values
+          // of lanes that do not store)
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int a = min(a0 + t, m - 1);
+            const int gr = per ? wrap(row0 + a, g.rows) : min(max(row0 + a, 0), g.rows - 1);
+            const int gcc = min(max(gc, 0), g.cols - 1);   // lanes >= m: any column
+            cv[t] *= we[a] * ld_off(A.dnorm, (unsigned)(gr * g.cols + gcc));
+          }
+        }
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
           const int a = a0 + t;
           const int gr = per ? wrap(row0 + a, g.rows) : row0 + a;
-          if (okc && a < m && (per || (gr >= 1 && gr <= g.rows - 2))) {
-            const long node = (long)gr * g.cols + gc;
-            float c = cv[t];
-            if (we) c *= we[a] * A.dnorm[node];
-            atomic_add(&A.u[node], c);
-          }
+          if (okc && a < m && (per || (gr >= 1 && gr <= g.rows - 2)))
+            atomic_add(&A.u[(long)gr * g.cols + gc], cv[t]);
         }
       }
     }
@@ -280,6 +351,8 @@ void launch_fdm_mfma(const FdmArgs<float> &a, bool fp16, hipStream_t s) {
     throw std::runtime_error("matrix-core Schwarz kernel: tile width outside [17, 48]");
   if (!a.mo.by || !a.mo.bx || !a.mo.ey || !a.mo.ex)
     throw std::runtime_error("matrix-core Schwarz kernel: operand tables missing");
+  if ((long)a.g.rows * a.g.cols >= (1L << 30))
+    throw std::runtime_error("matrix-core Schwarz kernel: node array of 2^30 words or more");
   if (fp16)
     launch_op<OpF16>(a, s);
   else
