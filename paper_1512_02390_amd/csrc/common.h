@@ -51,15 +51,19 @@ __device__ __forceinline__ T node_value_guarded(const T *__restrict__ a, int row
   return a[(long)row * cols + col];
 }
 
-// No branch on the boundary type either: the wrapped index is formed in both
-// cases (for Dirichlet it only matters where the node is a zero anyway).
+// No branch on the boundary type either: the wrapped index, clamped into the
+// array, is formed in both cases and always loaded (for Dirichlet it only
+// matters where the node is a zero anyway), and bitwise, not short-circuit,
+// operators form the test.  A branch here (on the uniform boundary type, or
+// around the index arithmetic) ends the scheduling region at every call, and
+// the loads of an unrolled loop of calls then wait one by one.
 template <typename T>
 __device__ __forceinline__ T node_value(const T *__restrict__ a, int row, int col, int rows,
                                         int cols, int periodic) {
-  const int rw = wrap(row, rows), cw = wrap(col, cols);
-  const bool ok = periodic || (row >= 1 && row <= rows - 2 && col >= 1 && col <= cols - 2);
-  const long idx = ok ? (long)rw * cols + cw : 0;
-  const T v = a[idx];
+  const int rw = min(max(wrap(row, rows), 0), rows - 1);
+  const int cw = min(max(wrap(col, cols), 0), cols - 1);
+  const bool ok = (periodic != 0) | ((row >= 1) & (row <= rows - 2) & (col >= 1) & (col <= cols - 2));
+  const T v = a[(long)rw * cols + cw];
   return ok ? v : T(0);
 }
 

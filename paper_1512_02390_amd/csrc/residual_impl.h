@@ -101,14 +101,10 @@ __device__ __forceinline__ void load_col(const T *__restrict__ u, int row0, int 
 template <typename T>
 __device__ __forceinline__ T coef_value(const T *__restrict__ a, int row, int col, int rows,
                                         int cols, int periodic) {
-  if (periodic) {
-    row = wrap(row, rows);
-    col = wrap(col, cols);
-  } else {
-    row = min(max(row, 0), rows - 1);
-    col = min(max(col, 0), cols - 1);
-  }
-  return a[(long)row * cols + col];
+  // both index forms, then a select (no branch: see node_value)
+  const int r = periodic ? wrap(row, rows) : min(max(row, 0), rows - 1);
+  const int c = periodic ? wrap(col, cols) : min(max(col, 0), cols - 1);
+  return a[(long)r * cols + c];
 }
 
 // Wavefronts per block of the residual kernels.  With one block per element
@@ -199,8 +195,11 @@ __global__ __launch_bounds__(64 * NW * KR) void k_residual(ResidualArgs<T> A) {
   if (act && w == 0 && (lane < P || (lane == P && c0 + W <= last_col))) {
     const int kk = lane < P ? lane : P + W;
     const int col = lane < P ? c0 - P + lane : c0 + W;
+    T hl[P];   // all loads first, then the LDS stores
 #pragma unroll
-    for (int a = 0; a < P; ++a) su[a][kk] = node_value(A.u, r0 + a, col, g.rows, g.cols, per);
+    for (int a = 0; a < P; ++a) hl[a] = node_value(A.u, r0 + a, col, g.rows, g.cols, per);
+#pragma unroll
+    for (int a = 0; a < P; ++a) su[a][kk] = hl[a];
   }
   // the first element row of the block recomputes the contribution of the
   // element below to its shared bottom row; the others take it from the
@@ -257,7 +256,7 @@ __global__ __launch_bounds__(64 * NW * KR) void k_residual(ResidualArgs<T> A) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const T sy = A.sy[ey];
+    const T sy = as_const(A.sy)[ey];
 #pragma unroll
     for (int t = 0; t < HR; ++t) {
       const int a = lo + t;
@@ -268,7 +267,10 @@ __global__ __launch_bounds__(64 * NW * KR) void k_residual(ResidualArgs<T> A) {
       T yp = sy * udot<T, P + 1>(orow, yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
-      const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
+      // (wave-uniform table reads through the constant space: scalar loads
+      // that need not wait for the previous row's store)
+      const T myr = as_const(A.my)[ey] * as_const(A.w)[a] +
+                    ((a == 0 && has_below) ? as_const(A.my)[max(eym, 0)] * as_const(A.w)[P] : T(0));
       const T au = myr * sxp(a, c) + mxc * yp;
       T v = A.f ? hv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
     const bool has_left = per || ex > 0;
     const int exm = per ? wrap(ex - 1, g.nx) : ex - 1;
     const T mxc = A.mx[ex] * A.w[al] + ((al == 0 && has_left) ? A.mx[exm] * A.w[P] : T(0));
-    const T sy = A.sy[ey];
+    const T sy = as_const(A.sy)[ey];
     // right-hand side and dot operand loaded before the first store (see k_residual)
     constexpr int HR = (P + NW - 1) / NW;
     T fv[HR], xv[HR];
@@ -461,7 +463,10 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
       T yp = sy * udot<T, P + 1>(orow, yv);
       if (a == 0) yp += extra_y;
       const int row = r0 + a;
-      const T myr = A.my[ey] * A.w[a] + ((a == 0 && has_below) ? A.my[eym] * A.w[P] : T(0));
+      // (wave-uniform table reads through the constant space: scalar loads
+      // that need not wait for the previous row's store)
+      const T myr = as_const(A.my)[ey] * as_const(A.w)[a] +
+                    ((a == 0 && has_below) ? as_const(A.my)[max(eym, 0)] * as_const(A.w)[P] : T(0));
       const T au = myr * sxp[a][c] + mxc * yp;
       T v = A.f ? fv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
