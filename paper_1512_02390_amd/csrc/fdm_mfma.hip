@@ -28,6 +28,7 @@
 #include "kernels.h"
 
 #include <stdexcept>
+#include <type_traits>
 
 namespace sem {
 namespace {
@@ -304,33 +305,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NB > 2 ? 3 :
       const int gc = per ? wrap(col0 + lane, g.cols) : col0 + lane;
       const bool okc = lane < m && (per || (gc >= 1 && gc <= g.cols - 2));
       const float wxn = okc ? (we ? we[m + lane] : A.wx[(long)ex * m + lane]) * back : 0.f;
-      // four rows per iteration: their LDS reads are issued together, and
-      // the atomics need no wait
+      // The tile's rows in groups of four (their LDS reads issued together),
+      // unrolled over the padded width so that per-row values stay in
+      // registers.  With per-element weights the row weights and the nodes'
+      // normalisation are loaded for all rows first, in one batch: a load
+      // between two atomics would make the wavefront wait for the atomics.
       constexpr int RB = 4;
-      for (int a0 = 0; a0 < m; a0 += RB) {
-        float cv[RB];
+      auto scatter = [&](auto learned) {
+        constexpr bool kW = decltype(learned)::value;
+        float fw[kW ? N : 1];
+        if constexpr (kW) {
+          const int gcc = min(max(gc, 0), g.cols - 1);   // lanes >= m: any column
 #pragma unroll
-        for (int t = 0; t < RB; ++t) cv[t] = tile[(a0 + t) * LS + lane] * wxn;   // rows < N
-        if (we) {
-          // per-element weights: the row weights and the normalisation of
-          // the RB nodes loaded together (clamped addresses, unused values
-          // of lanes that do not store)
-#pragma unroll
-          for (int t = 0; t < RB; ++t) {
-            const int a = min(a0 + t, m - 1);
-            const int gr = per ? wrap(row0 + a, g.rows) : min(max(row0 + a, 0), g.rows - 1);
-            const int gcc = min(max(gc, 0), g.cols - 1);   // lanes >= m: any column
-            cv[t] *= we[a] * ld_off(A.dnorm, (unsigned)(gr * g.cols + gcc));
+          for (int a = 0; a < N; ++a) {
+            const int ac = min(a, m - 1);
+            const int gr = per ? wrap(row0 + ac, g.rows) : min(max(row0 + ac, 0), g.rows - 1);
+            fw[a] = we[ac] * ld_off(A.dnorm, (unsigned)(gr * g.cols + gcc));
           }
         }
 #pragma unroll
-        for (int t = 0; t < RB; ++t) {
-          const int a = a0 + t;
-          const int gr = per ? wrap(row0 + a, g.rows) : row0 + a;
-          if (okc && a < m && (per || (gr >= 1 && gr <= g.rows - 2)))
-            atomic_add(&A.u[(long)gr * g.cols + gc], cv[t]);
+        for (int a0 = 0; a0 < N; a0 += RB) {
+          if (a0 >= m) break;
+          float cv[RB];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) cv[t] = tile[(a0 + t) * LS + lane] * wxn;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int a = a0 + t;
+            const int gr = per ? wrap(row0 + a, g.rows) : row0 + a;
+            if (okc && a < m && (per || (gr >= 1 && gr <= g.rows - 2))) {
+              float c = cv[t];
+              if constexpr (kW) c *= fw[a];
+              atomic_add(&A.u[(long)gr * g.cols + gc], c);
+            }
+          }
         }
-      }
+      };
+      if (we)
+        scatter(std::true_type{});
+      else
+        scatter(std::false_type{});
     }
   }
 }
