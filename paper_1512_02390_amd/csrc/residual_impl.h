@@ -447,13 +447,19 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
     const T sy = as_const(A.sy)[ey];
     // right-hand side and dot operand loaded before the first store (see k_residual)
     constexpr int HR = (P + NW - 1) / NW;
-    T fv[HR], xv[HR];
+    // (f and dot_x are never both given: one array of loads serves either.
+    // The loads sit in one block under the uniform test, with rows past the
+    // wave's share clamped to a valid one: a branch per load would end the
+    // scheduling region at each, and the loads would wait one by one.)
+    const T *hsrc = A.f ? A.f : A.dot_x;
+    T hv[HR];
+    if (hsrc) {
 #pragma unroll
-    for (int t = 0; t < HR; ++t) {
-      const long idx = (long)(r0 + lo + t) * g.cols + gc;
-      const bool on = lo + t < hi;
-      fv[t] = (on && A.f) ? A.f[idx] : T(0);
-      xv[t] = (on && A.dot_x) ? A.dot_x[idx] : T(0);
+      for (int t = 0; t < HR; ++t)
+        hv[t] = hsrc[(long)(r0 + max(min(lo + t, hi - 1), 0)) * g.cols + gc];
+    } else {
+#pragma unroll
+      for (int t = 0; t < HR; ++t) hv[t] = T(0);
     }
 #pragma unroll
     for (int t = 0; t < HR; ++t) {
@@ -468,10 +474,10 @@ __global__ __launch_bounds__(64 * NW) void k_residual_nu(ResidualArgs<T> A) {
       const T myr = as_const(A.my)[ey] * as_const(A.w)[a] +
                     ((a == 0 && has_below) ? as_const(A.my)[max(eym, 0)] * as_const(A.w)[P] : T(0));
       const T au = myr * sxp[a][c] + mxc * yp;
-      T v = A.f ? fv[t] - au : au;
+      T v = A.f ? hv[t] - au : au;
       if (!per && (row == 0 || gc == 0)) v = T(0);
       A.out[(long)row * g.cols + gc] = v;
-      dsum += (double)v * (double)xv[t];
+      if (A.dot_x) dsum += (double)v * (double)hv[t];
     }
     if (w == 0 && !per && ey == g.ny - 1) A.out[(long)(g.rows - 1) * g.cols + gc] = T(0);
   }
